@@ -1,0 +1,220 @@
+/*
+ * sfft.h -- C ABI of the SFFT image-subtraction library for AMD MI355X (gfx950).
+ *
+ * The library fits, for a reference image R and a science image S of
+ * N0 x N1 pixels, a spatially varying convolution kernel and a polynomial
+ * differential background so that R (x) K + B approximates S, then forms the
+ * difference image (Hu et al. 2022, "Image Subtraction in Fourier Space",
+ * Sec. 2.2):
+ *
+ *   D(x) = S(x) - sum_{ij ab} a_ijab (R^ij o K_ab)(x) - sum_pq b_pq T^pq(x)   (Eq. 12)
+ *
+ * with the delta-function basis K_00 = delta, K_ab = delta(. - (a,b)) - delta
+ * (Eq. 3-4), kernel variation a_ijab x^i y^j with i + j <= DK (Eq. 5-6),
+ * background b_pq x^p y^q with p + q <= DB (Eq. 2), weights applied at the
+ * source pixel (Eq. 11, App. A) and circular convolution o (Eq. 12). The
+ * least-squares coefficients solve the normal equations of Eq. 18, whose
+ * elements are built from correlation-lag tables (App. B, Eq. B5-B16)
+ * computed from FFTs of the weighted images, spectral products and pruned
+ * inverse FFTs.
+ *
+ * Conventions (shared by every entry point):
+ *  - Images are C row-major arrays of n0 x n1 elements; x (the paper's first
+ *    index) is axis 0, y is axis 1.
+ *  - Polynomial coordinates are centred and normalised:
+ *    c(x) = (2x - (N-1)) / (N-1) in [-1, 1]. This spans the same model as the
+ *    raw pixel indices of Eq. 2 and 6 (so D is the same) with a far better
+ *    conditioned normal matrix; coefficients refer to these coordinates.
+ *  - Kernel offsets a in [-w0, w0], b in [-w1, w1]; K_ab shifts the image by
+ *    +(a, b): (R o K_ab)(x) = R(x - (a,b)) - R(x) for (a,b) != 0 (Eq. 14).
+ *  - Unknown order: kernel term k over (i, j) with i ascending then j
+ *    ascending; inside k the offset (a, b) row-major over the L0 x L1 grid,
+ *    skipping (k > 0, a = b = 0) when const_phot_ratio is set; then the
+ *    background terms (p, q) in the same order. Coefficients are the
+ *    pixel-unit a-ring of Eq. 13 (a = N0 N1 a-ring).
+ *  - Supported sizes: n0, n1 = 2^a 3^b, multiples of 16, 16 <= n <= 8192;
+ *    2 w + 1 <= n; 0 <= DK, DB <= 4; w0, w1 <= 16.
+ *
+ * Memory and streams: every image, matrix and vector argument is a device
+ * pointer owned by the caller (for instance the storage of a PyTorch
+ * tensor). The context owns its plans, device workspaces and twiddle tables.
+ * Calls are stream-ordered on the HIP stream passed as `stream` (NULL = the
+ * null stream) and return without waiting for the GPU; errors found on the
+ * host are returned at once. Direct calls that share one context must be
+ * ordered on one stream by the caller (they share the context's workspace).
+ * The submit/poll engine has its own per-request workspaces and streams.
+ *
+ * Errors detected on the device (a normal matrix that is not positive
+ * definite, non-finite input) are recorded in the context and returned by
+ * sfft_sync(); the affected coefficients are set to NaN.
+ */
+#ifndef SFFT_H
+#define SFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfft_ctx sfft_ctx;
+
+/* Status codes. */
+enum {
+    SFFT_OK = 0,
+    SFFT_PENDING = 1,          /* sfft_poll: request not finished yet */
+    SFFT_E_INVAL = -1,         /* invalid argument or parameter set */
+    SFFT_E_NOMEM = -2,         /* workspace does not fit the HBM budget */
+    SFFT_E_NOT_SPD = -3,       /* normal matrix not positive definite */
+    SFFT_E_NONFINITE = -4,     /* NaN or Inf in the inputs / normal matrix */
+    SFFT_E_UNSUPPORTED = -5,   /* size not of the form 2^a 3^b, too large, ... */
+    SFFT_E_HIP = -6,           /* HIP runtime error */
+    SFFT_E_NOTFOUND = -7       /* unknown request ticket */
+};
+
+/* Arithmetic of the hot path. */
+enum {
+    SFFT_FP64 = 0,   /* every stage in FP64 */
+    SFFT_MIXED = 1   /* FFTs and spectral products in FP32 with FP32 accumulation;
+                        lag tables, normal-matrix accumulation, Cholesky solve and
+                        one iterative-refinement step in FP64 */
+};
+
+/* Element type of the image arrays (inputs and the difference image). */
+enum { SFFT_F32 = 0, SFFT_F64 = 1 };
+
+/* Problem parameters (Table A1: -KerPolyOrder = dk, -BGPolyOrder = db,
+ * -ConstPhotRatio = const_phot_ratio; the kernel half widths w0, w1 are
+ * chosen by the caller, e.g. -KerHWRatio times the seeing FWHM). */
+typedef struct {
+    int32_t n0, n1;            /* image shape (rows, columns) */
+    int32_t w0, w1;            /* kernel half widths: L = 2w + 1 */
+    int32_t dk;                /* kernel polynomial degree (Eq. 6) */
+    int32_t db;                /* background polynomial degree (Eq. 2) */
+    int32_t const_phot_ratio;  /* 1: constant kernel sum across the field */
+    int32_t precision;         /* SFFT_FP64 or SFFT_MIXED */
+    int32_t dtype;             /* SFFT_F32 or SFFT_F64 */
+} sfft_params;
+
+/* Create a context on HIP device `device`. hbm_budget_bytes caps the device
+ * memory the context may allocate for workspaces (0 = no cap). Returns
+ * SFFT_OK and *out, or an error. */
+int sfft_create(sfft_ctx** out, int device, size_t hbm_budget_bytes);
+
+/* Destroy a context: waits for its work, frees every workspace. */
+void sfft_destroy(sfft_ctx* ctx);
+
+/* Number of unknowns N_u = P L0 L1 - [const_phot] (P - 1) + Q with
+ * P = (DK+1)(DK+2)/2, Q = (DB+1)(DB+2)/2; negative on invalid parameters. */
+int64_t sfft_num_unknowns(const sfft_params* p);
+
+/* Validate a parameter set: SFFT_OK, SFFT_E_INVAL or SFFT_E_UNSUPPORTED. */
+int sfft_check_params(const sfft_params* p);
+
+/* Device bytes one workspace for `p` occupies (negative on invalid p). */
+int64_t sfft_workspace_bytes(const sfft_params* p);
+
+/* Normal equations of the fit pair (the masked images of Sec. 3):
+ * G (N_u x N_u, row-major, FP64, exactly symmetric) and h (N_u, FP64) in
+ * pixel units, G_uv = sum_x Phi_u Phi_v and h_u = sum_x Phi_u S_fit
+ * (Eq. 18-24 through App. B). r_fit, s_fit: n0*n1 elements of `dtype`. */
+int sfft_build_system(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void* s_fit,
+                      double* G, double* h, void* stream);
+
+/* Solve G coef = h (Jacobi-scaled FP64 Cholesky). When precision is
+ * SFFT_MIXED and r_fit, s_fit are given, one iterative-refinement step
+ * follows: the gradient Phi^T (S_fit - Phi coef) of the current difference
+ * image is recomputed from the images and the correction is solved with the
+ * same factor. coef: N_u doubles, kernel coefficients then background. */
+int sfft_solve(sfft_ctx* ctx, const sfft_params* p, const double* G, const double* h,
+               const void* r_fit, const void* s_fit, double* coef, void* stream);
+
+/* Difference image of the apply pair (the unmasked images, Sec. 3):
+ * d = s - sum_k (c0^i c1^j r) o kappa_k - B with the stamps kappa_k of
+ * `coef` (Eq. 12-13). r, s, d: n0*n1 elements of `dtype`. */
+int sfft_subtract(sfft_ctx* ctx, const sfft_params* p, const void* r, const void* s,
+                  const double* coef, void* d, void* stream);
+
+/* Whole hot path in one call: build on (r_fit, s_fit), solve (with the
+ * refinement step in SFFT_MIXED), subtract on (r, s). Row and column
+ * transforms of the fit pair are reused inside the call. coef may be NULL
+ * (the context keeps its own copy); G and h are internal. */
+int sfft_run(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void* s_fit,
+             const void* r, const void* s, double* coef, void* d, void* stream);
+
+/* Wait for `stream` and report device-side errors recorded since the last
+ * sfft_sync on this context (SFFT_E_NOT_SPD, SFFT_E_NONFINITE) or SFFT_OK. */
+int sfft_sync(sfft_ctx* ctx, void* stream);
+
+/* Lag tables of the fit pair in pixel units, FP64 (diagnostics):
+ * omega [P(P+1)/2][4w0+1][4w1+1] for kernel-term pairs kb <= k (Eq. B6),
+ * theta [P][2w0+1][2w1+1] (Eq. B14), lambda [P][Q][2w0+1][2w1+1] (Eq. B8),
+ * cmat [Q][Q] (Eq. B11), evec [Q] (Eq. B15). Any pointer may be NULL. */
+int sfft_lag_tables(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void* s_fit,
+                    double* omega, double* theta, double* lambda, double* cmat, double* evec,
+                    void* stream);
+
+/* Batched complex line transform of the library's FFT engine (diagnostics):
+ * `lines` lines of n complex values (interleaved re, im of `dtype`),
+ * contiguous; sign -1 forward (e^-), +1 unnormalised inverse. */
+int sfft_fft_lines(sfft_ctx* ctx, int n, int lines, int sign, int dtype, const void* in, void* out,
+                   void* stream);
+
+/* ---- stage timers (tracing) ------------------------------------------ */
+
+/* Enable (1) or disable (0) per-stage timing of direct calls: each stage of
+ * the hot path (row transform, column transform, lag products, lag rows,
+ * background blocks, gather, Cholesky, triangular solves, refinement,
+ * stencil, row inverse) records HIP events on its stream. Waits for the
+ * device and clears previous records. */
+int sfft_profile(sfft_ctx* ctx, int enable);
+
+/* Waits for the device and aggregates the recorded stages in first-seen
+ * order: names[32*i] (NUL-terminated), total_ms[i] summed over calls,
+ * counts[i] calls. Returns the number of distinct stages (may exceed
+ * max_stages; only max_stages are written) or a negative error. */
+int sfft_profile_read(sfft_ctx* ctx, int max_stages, char* names, double* total_ms, int* counts);
+
+/* ---- serving engine: continuous batching of independent pairs ---------- */
+
+/* One request: the fit pair, the apply pair, the outputs. All device
+ * pointers stay owned by the caller and must stay valid until the request
+ * completes. coef (N_u doubles) may be NULL. */
+typedef struct {
+    sfft_params p;
+    const void* r_fit;
+    const void* s_fit;
+    const void* r;
+    const void* s;
+    double* coef;
+    void* d;
+} sfft_request;
+
+/* Configure the engine: `slots` concurrent requests (each on its own HIP
+ * stream with its own workspace), admission against the context's HBM
+ * budget. Called once before the first submit; 0 slots = default (4). */
+int sfft_engine_config(sfft_ctx* ctx, int slots);
+
+/* Queue a request. Returns SFFT_OK and a ticket; SFFT_E_NOMEM if the
+ * request can never fit the budget; SFFT_E_INVAL/UNSUPPORTED on bad params.
+ * Requests are admitted in arrival order as slots and memory free up and
+ * run concurrently on the device. */
+int sfft_submit(sfft_ctx* ctx, const sfft_request* req, uint64_t* ticket);
+
+/* SFFT_PENDING while the request is queued or running, then its final
+ * status (SFFT_OK or an error); SFFT_E_NOTFOUND for an unknown ticket.
+ * A finished ticket is forgotten after its status has been returned once. */
+int sfft_poll(sfft_ctx* ctx, uint64_t ticket);
+
+/* Block until the request finishes; returns its final status. */
+int sfft_wait(sfft_ctx* ctx, uint64_t ticket);
+
+/* Human-readable text of a status code (static string). */
+const char* sfft_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFFT_H */

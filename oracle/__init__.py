@@ -59,6 +59,8 @@ def lib():
             L.orc_build.argtypes = [dp, dp, i, i, i, i, i, i, i, dp, dp]
             L.orc_g_entry.restype = ctypes.c_double
             L.orc_g_entry.argtypes = [dp, i, i, i, i, i, i, i, ctypes.c_long, ctypes.c_long]
+            L.orc_phi_dot.restype = ctypes.c_double
+            L.orc_phi_dot.argtypes = [dp, dp, i, i, i, i, i, i, i, ctypes.c_long]
             L.orc_solve.argtypes = [dp, dp, ctypes.c_long, dp]
             L.orc_stamps.argtypes = [dp, i, i, i, i, dp]
             L.orc_subtract.argtypes = [dp, dp, i, i, i, i, i, i, i, dp, dp]
@@ -175,6 +177,13 @@ def build_system(r, s, w0, w1, dk, db, const_phot=0):
 def g_entry(r, w0, w1, dk, db, const_phot, u, v):
     r, rp = _d(r)
     return float(lib().orc_g_entry(rp, r.shape[0], r.shape[1], w0, w1, dk, db, const_phot, u, v))
+
+
+def phi_dot(r, img, w0, w1, dk, db, const_phot, u):
+    """Component u of Phi^T img (h_u for img = S; the gradient for img = D)."""
+    r, rp = _d(r)
+    img, ip = _d(img)
+    return float(lib().orc_phi_dot(rp, ip, r.shape[0], r.shape[1], w0, w1, dk, db, const_phot, u))
 
 
 def solve(G, h):

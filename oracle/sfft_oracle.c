@@ -354,6 +354,44 @@ double orc_g_entry(const double* r, int n0, int n1, int w0, int w1, int dk, int 
     return acc;
 }
 
+/* sum_x Phi_u(x) img(x) for one unknown u (one component of Phi^T img):
+ * with img = S it is h_u; with img = S - Phi c it is the gradient of the
+ * objective at c (Eq. 16-17), zero at the least-squares optimum. */
+double orc_phi_dot(const double* r, const double* img, int n0, int n1, int w0, int w1, int dk,
+                   int db, int cp, long u) {
+    long nk = kernel_unknowns(w0, w1, dk, cp, NULL, NULL, NULL);
+    int k = -1, a = 0, b = 0, i, j;
+    if (u < nk) {
+        int* K = (int*)malloc(sizeof(int) * nk * 3);
+        kernel_unknowns(w0, w1, dk, cp, K, K + nk, K + 2 * nk);
+        k = K[u];
+        a = K[nk + u];
+        b = K[2 * nk + u];
+        free(K);
+        orc_term(dk, k, &i, &j);
+    } else {
+        orc_term(db, (int)(u - nk), &i, &j);
+    }
+    double acc = 0.0;
+#pragma omp parallel for reduction(+ : acc) schedule(static)
+    for (long x0 = 0; x0 < n0; ++x0) {
+        double row = 0.0;
+        for (long x1 = 0; x1 < n1; ++x1) {
+            double f;
+            if (k >= 0) {
+                long s0 = imod(x0 - a, n0), s1 = imod(x1 - b, n1);
+                f = pow(orc_coord(s0, n0), i) * pow(orc_coord(s1, n1), j) * r[s0 * n1 + s1];
+                if (a || b) f -= pow(orc_coord(x0, n0), i) * pow(orc_coord(x1, n1), j) * r[x0 * n1 + x1];
+            } else {
+                f = pow(orc_coord(x0, n0), i) * pow(orc_coord(x1, n1), j);
+            }
+            row += f * img[x0 * n1 + x1];
+        }
+        acc += row;
+    }
+    return acc;
+}
+
 /* Solve G c = h: Jacobi scaling d = diag(G)^-1/2, textbook Cholesky of
  * D G D, two triangular solves, c = D y. Returns ORC_ENOTSPD on a
  * non-positive pivot. */

@@ -1,0 +1,702 @@
+// Host runtime of the SFFT library: parameter validation, per-geometry plans
+// (line plans, twiddle tables, device workspaces), the stream-ordered
+// pipeline of the hot path, and the C ABI declared in sfft.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "engine.hpp"
+#include "runtime.hpp"
+
+namespace sfft {
+
+// ------------------------------------------------------------ parameters
+
+static int nterms(int d) { return (d + 1) * (d + 2) / 2; }
+
+static bool radix23(int n, int* a2, int* a3) {
+    int a = 0, b = 0;
+    while (n > 1 && n % 2 == 0) { n /= 2; ++a; }
+    while (n > 1 && n % 3 == 0) { n /= 3; ++b; }
+    *a2 = a;
+    *a3 = b;
+    return n == 1;
+}
+
+int check_params(const sfft_params* p) {
+    if (!p) return SFFT_E_INVAL;
+    if (p->n0 < 16 || p->n1 < 16 || p->w0 < 0 || p->w1 < 0 || p->dk < 0 || p->db < 0)
+        return SFFT_E_INVAL;
+    if (p->dk > 4 || p->db > 4 || p->w0 > 16 || p->w1 > 16) return SFFT_E_UNSUPPORTED;
+    if (2 * p->w0 + 1 > p->n0 || 2 * p->w1 + 1 > p->n1) return SFFT_E_INVAL;
+    if (p->precision != SFFT_FP64 && p->precision != SFFT_MIXED) return SFFT_E_INVAL;
+    if (p->dtype != SFFT_F32 && p->dtype != SFFT_F64) return SFFT_E_INVAL;
+    if (p->const_phot_ratio != 0 && p->const_phot_ratio != 1) return SFFT_E_INVAL;
+    int a, b;
+    for (int n : {p->n0, p->n1}) {
+        if (n % 16 || n > 8192 || !radix23(n, &a, &b)) return SFFT_E_UNSUPPORTED;
+    }
+    // 4w+1 lag rows must stay distinct modulo N (torus wrap of the lag range)
+    if (4 * p->w0 + 1 > p->n0 || 4 * p->w1 + 1 > p->n1) return SFFT_E_UNSUPPORTED;
+    return SFFT_OK;
+}
+
+int64_t num_unknowns(const sfft_params* p) {
+    if (!p || p->w0 < 0 || p->w1 < 0 || p->dk < 0 || p->db < 0) return -1;
+    const int64_t P = nterms(p->dk), Q = nterms(p->db);
+    const int64_t L = (int64_t)(2 * p->w0 + 1) * (2 * p->w1 + 1);
+    return P * L - (p->const_phot_ratio ? (P - 1) : 0) + Q;
+}
+
+static Geom make_geom(const sfft_params* p) {
+    Geom g{};
+    g.n0 = p->n0;
+    g.n1 = p->n1;
+    g.h = p->n1 / 2 + 1;
+    const int elt = p->precision == SFFT_MIXED ? 8 : 16;   // bytes per complex
+    const int line = 256 / elt;                             // complex per 256 B
+    g.hp = (g.h + line - 1) / line * line;
+    g.w0 = p->w0;
+    g.w1 = p->w1;
+    g.dk = p->dk;
+    g.db = p->db;
+    g.cp = p->const_phot_ratio;
+    g.P = nterms(p->dk);
+    g.Q = nterms(p->db);
+    g.L0 = 2 * p->w0 + 1;
+    g.L1 = 2 * p->w1 + 1;
+    g.nu = (int)num_unknowns(p);
+    g.nk = g.nu - g.Q;
+    g.npair = g.P * (g.P + 1) / 2;
+    g.nprod = g.npair + g.P;
+    g.nr = p->dk + 2;
+    g.D0 = 4 * p->w0 + 1;
+    g.D1 = 4 * p->w1 + 1;
+    return g;
+}
+
+static LinePlan make_line_plan(int n) {
+    LinePlan lp{};
+    lp.n = n;
+    int a, b;
+    radix23(n, &a, &b);
+    int np = 0;
+    while (a >= 4) { lp.radix[np++] = 16; a -= 4; }
+    if (a == 3) lp.radix[np++] = 8;
+    else if (a == 2) lp.radix[np++] = 4;
+    else if (a == 1) lp.radix[np++] = 2;
+    while (b-- > 0) lp.radix[np++] = 3;
+    lp.npass = np;
+    lp.tl = n / kElemsPerThread;
+    lp.lpw = lp.tl >= 256 ? 1 : 256 / lp.tl;
+    return lp;
+}
+
+size_t workspace_bytes(const sfft_params* p) {
+    Geom g = make_geom(p);
+    Workspace w;
+    const bool mixed = p->precision == SFFT_MIXED;
+    return carve(w, g, mixed ? 8 : 16, mixed ? 4 : 8, nullptr);
+}
+
+static hipError_t make_twiddles(int n, bool mixed, Twiddles& t) {
+    std::vector<double> c(n), s(n);
+    for (int k = 0; k < n; ++k) {
+        const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)k / (long double)n;
+        c[k] = (double)cosl(ang);
+        s[k] = (double)sinl(ang);
+    }
+    hipError_t e;
+    if (mixed) {
+        std::vector<cx<float>> v(n);
+        for (int k = 0; k < n; ++k) v[k] = {(float)c[k], (float)-s[k]};
+        e = hipMalloc(&t.tw, n * sizeof(cx<float>));
+        if (e) return e;
+        e = hipMemcpy(t.tw, v.data(), n * sizeof(cx<float>), hipMemcpyHostToDevice);
+    } else {
+        std::vector<cx<double>> v(n);
+        for (int k = 0; k < n; ++k) v[k] = {c[k], -s[k]};
+        e = hipMalloc(&t.tw, n * sizeof(cx<double>));
+        if (e) return e;
+        e = hipMemcpy(t.tw, v.data(), n * sizeof(cx<double>), hipMemcpyHostToDevice);
+    }
+    if (e) return e;
+    std::vector<double> vp(2 * n);
+    for (int k = 0; k < n; ++k) {
+        vp[2 * k] = c[k];
+        vp[2 * k + 1] = s[k];
+    }
+    e = hipMalloc(&t.twp, 2 * n * sizeof(double));
+    if (e) return e;
+    return hipMemcpy(t.twp, vp.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice);
+}
+
+static void free_twiddles(Twiddles& t) {
+    if (t.tw) (void)hipFree(t.tw);
+    if (t.twp) (void)hipFree(t.twp);
+    t.tw = nullptr;
+    t.twp = nullptr;
+}
+
+}  // namespace sfft
+
+using namespace sfft;
+
+namespace sfft {
+
+static int hip_status(hipError_t e) { return e == hipSuccess ? SFFT_OK : SFFT_E_HIP; }
+
+// Twiddles are shared by every plan of the context with the same length.
+static int get_twiddles(sfft_ctx* ctx, int n, bool mixed, Twiddles* out) {
+    auto key = std::make_pair(n, mixed ? 1 : 0);
+    auto it = ctx->twid.find(key);
+    if (it == ctx->twid.end()) {
+        Twiddles t;
+        hipError_t e = make_twiddles(n, mixed, t);
+        if (e != hipSuccess) {
+            free_twiddles(t);
+            return SFFT_E_HIP;
+        }
+        it = ctx->twid.emplace(key, t).first;
+    }
+    *out = it->second;
+    return SFFT_OK;
+}
+
+// Allocate a plan (with its workspace) against the context budget. Caller
+// holds ctx->mu.
+int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    auto pl = std::make_unique<Plan>();
+    pl->p = *p;
+    pl->g = make_geom(p);
+    pl->lp0 = make_line_plan(p->n0);
+    pl->lp1 = make_line_plan(p->n1);
+    pl->device = ctx->device;
+    const bool mixed = p->precision == SFFT_MIXED;
+    const size_t bytes = carve(pl->ws, pl->g, mixed ? 8 : 16, mixed ? 4 : 8, nullptr);
+    if (ctx->budget && ctx->used + bytes > ctx->budget) return SFFT_E_NOMEM;
+    rc = get_twiddles(ctx, p->n0, mixed, &pl->t0);
+    if (!rc) rc = get_twiddles(ctx, p->n1, mixed, &pl->t1);
+    if (rc) return rc;
+    char* base = nullptr;
+    if (hipMalloc(&base, bytes) != hipSuccess) return SFFT_E_NOMEM;
+    carve(pl->ws, pl->g, mixed ? 8 : 16, mixed ? 4 : 8, base);
+    pl->ws.base = base;
+    pl->ws.bytes = bytes;
+    ctx->used += bytes;
+    out = std::move(pl);
+    return SFFT_OK;
+}
+
+void destroy_plan(sfft_ctx* ctx, std::unique_ptr<Plan>& pl) {
+    if (!pl) return;
+    if (pl->ws.base) (void)hipFree(pl->ws.base);
+    ctx->used -= pl->ws.bytes;
+    pl.reset();
+}
+
+static int direct_plan(sfft_ctx* ctx, const sfft_params* p, Plan** out) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    auto k = key_of(p);
+    auto it = ctx->plans.find(k);
+    if (it == ctx->plans.end()) {
+        std::unique_ptr<Plan> pl;
+        rc = create_plan(ctx, p, pl);
+        if (rc) return rc;
+        it = ctx->plans.emplace(k, std::move(pl)).first;
+    }
+    it->second->p.dtype = p->dtype;
+    it->second->prof = &ctx->prof;
+    *out = it->second.get();
+    return SFFT_OK;
+}
+
+// ------------------------------------------------------------ pipeline
+
+template <typename T>
+static cx<T>* cxp(void* p) { return reinterpret_cast<cx<T>*>(p); }
+
+static RowSources pair_sources(const Geom& g, bool pedestal) {
+    RowSources src{};
+    src.n = g.nr;
+    for (int j = 0; j <= g.dk; ++j) {
+        src.pow[j] = j;
+        src.img[j] = 0;
+        src.out[j] = j;
+        src.ped[j] = pedestal ? 0 : -1;
+    }
+    src.pow[g.dk + 1] = 0;
+    src.img[g.dk + 1] = 1;
+    src.out[g.dk + 1] = g.dk + 1;
+    src.ped[g.dk + 1] = pedestal ? 1 : -1;
+    return src;
+}
+
+// Stage 1 of the build, FP64: polynomial-correlation tables of R (|d| <= 2w)
+// and S (|d| <= w), 1-D polynomial sums, and the pedestals (image means).
+template <typename Tin>
+static hipError_t poly_tables(Plan& pl, const Tin* r, const Tin* s, hipStream_t st) {
+    const Geom& g = pl.g;
+    Workspace& w = pl.ws;
+    const int dm = poly_degree(g);
+    StageTimer t_(pl.prof, "background", st);
+    hipError_t e = launch_polyrow<Tin>(g, r, g.dk, dm, 2 * g.w1, w.vrow, st);
+    if (!e) e = launch_polycorr(g, w.vrow, g.dk, dm, 2 * g.w0, 2 * g.w1, w.piR, st);
+    if (!e) e = launch_polyrow<Tin>(g, s, 0, dm, g.w1, w.vrow, st);
+    if (!e) e = launch_polycorr(g, w.vrow, 0, dm, g.w0, g.w1, w.piS, st);
+    if (!e) e = launch_polysum(g, dm, w.sig0, w.sig1, w.pw, st);
+    if (!e) e = launch_pedestal(g, w.piR, dm, w.piS, w.ped, st);
+    return e;
+}
+
+// Row and column transforms of the pedestal-free fit pair: Z[0..nr), X[0..P].
+template <typename T, typename Tin>
+static hipError_t forward_fit(Plan& pl, const Tin* r, const Tin* s, hipStream_t st) {
+    const Geom& g = pl.g;
+    Workspace& w = pl.ws;
+    hipError_t e;
+    {
+        StageTimer t_(pl.prof, "rowfwd", st);
+        e = launch_rowfwd<T, Tin>(g, pl.lp1, pair_sources(g, true), r, s, w.ped, cxp<T>(w.Z),
+                                  cxp<T>(pl.t1.tw), st);
+    }
+    if (e) return e;
+    ColJobs jobs{};
+    jobs.narr = g.nr;
+    for (int a = 0; a <= g.dk; ++a) {
+        jobs.arr[a] = a;
+        jobs.nw[a] = g.dk - a + 1;
+        for (int i = 0; i < jobs.nw[a]; ++i) jobs.spec[a][i] = term_index(g.dk, i, a);
+    }
+    jobs.arr[g.dk + 1] = g.dk + 1;
+    jobs.nw[g.dk + 1] = 1;
+    jobs.spec[g.dk + 1][0] = g.P;
+    StageTimer t_(pl.prof, "colfwd", st);
+    return launch_colfwd<T>(g, pl.lp0, jobs, cxp<T>(w.Z), cxp<T>(w.X), cxp<T>(pl.t0.tw), st);
+}
+
+// Pedestal tables, transforms, products and pruned inverses, then the exact
+// FP64 pedestal corrections: Omega, Theta, Lambda, C, E of the fit pair.
+template <typename T, typename Tin>
+static hipError_t lag_tables(Plan& pl, const Tin* r, const Tin* s, hipStream_t st) {
+    const Geom& g = pl.g;
+    Workspace& w = pl.ws;
+    hipError_t e = poly_tables<Tin>(pl, r, s, st);
+    if (!e) e = forward_fit<T, Tin>(pl, r, s, st);
+    if (!e) {
+        StageTimer t_(pl.prof, "lagcol", st);
+        e = launch_lagcol<T>(g, pl.lp0, 0, g.nprod, g.P, cxp<T>(w.X), cxp<T>(w.Cl), cxp<T>(pl.t0.tw), st);
+    }
+    if (!e) {
+        StageTimer t_(pl.prof, "lagrow", st);
+        e = launch_lagrow<T>(g, 0, g.nprod, cxp<T>(w.Cl), pl.t1.twp, w.omega, w.theta, st);
+    }
+    if (!e) {
+        StageTimer t_(pl.prof, "lagfix", st);
+        e = launch_lagfix(g, 0, w.ped, w.piR, w.piS, w.sig0, w.sig1, w.pw, poly_degree(g), w.omega,
+                          w.theta, w.lam, w.cmat, w.evec, st);
+    }
+    return e;
+}
+
+template <typename T, typename Tin>
+static hipError_t build(Plan& pl, const Tin* r, const Tin* s, double* G, double* h, hipStream_t st) {
+    hipError_t e = lag_tables<T, Tin>(pl, r, s, st);
+    Workspace& w = pl.ws;
+    StageTimer t_(pl.prof, "gather", st);
+    if (!e) e = launch_gather(pl.g, w.omega, w.theta, w.lam, w.cmat, w.evec, G, h, 0, st);
+    return e;
+}
+
+static hipError_t ensure_ytab(Plan& pl, hipStream_t st) {
+    if (pl.ws.ytab_ready) return hipSuccess;
+    hipError_t e = launch_ytab(pl.g, pl.t1.twp, pl.ws.ytab, st);
+    if (!e) pl.ws.ytab_ready = true;
+    return e;
+}
+
+// D from the row spectra in Z (slots 0..DK of R, slot zs of S; with the
+// pedestals of w.ped removed when `pedestal`) and the coefficients.
+template <typename T, typename Tout>
+static hipError_t difference(Plan& pl, int zs, bool pedestal, const double* coef, Tout* d,
+                             hipStream_t st) {
+    const Geom& g = pl.g;
+    Workspace& w = pl.ws;
+    hipError_t e = ensure_ytab(pl, st);
+    {
+        StageTimer t_(pl.prof, "stencil", st);
+        if (!e) e = launch_stamps(g, coef, w.kap, st);
+        if (!e) e = launch_stamp_spectra<T>(g, w.kap, pl.t1.twp, cxp<T>(w.Kt), st);
+        if (!e) e = launch_stencil<T>(g, cxp<T>(w.Z), zs, cxp<T>(w.Kt), pedestal ? w.ped : nullptr,
+                                      w.ytab, cxp<T>(w.Dt), st);
+    }
+    if (!e) {
+        StageTimer t_(pl.prof, "rowinv", st);
+        e = launch_rowinv<T, Tout>(g, pl.lp1, cxp<T>(w.Dt), d, coef + g.nk, cxp<T>(pl.t1.tw), st);
+    }
+    return e;
+}
+
+// Factor G (Jacobi-scaled) and solve into coef.
+static hipError_t factor_solve(Plan& pl, const double* G, const double* h, double* coef,
+                               hipStream_t st) {
+    const int n = pl.g.nu;
+    Workspace& w = pl.ws;
+    hipError_t e;
+    {
+        StageTimer t_(pl.prof, "cholesky", st);
+        e = launch_jacobi(n, G, h, w.L, w.dsc, w.rhs, w.flag, st);
+        if (!e) e = launch_cholesky(n, w.L, w.flag, st);
+    }
+    if (!e) {
+        StageTimer t_(pl.prof, "trsv", st);
+        e = hipMemcpyAsync(w.rhs, h, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (!e) e = launch_chol_solve(n, w.L, w.dsc, w.rhs, coef, 0, w.flag, st);
+    }
+    return e;
+}
+
+// One refinement step: gradient Phi^T (S_fit - Phi coef) of the current
+// difference image of the fit pair (Z, X, ped hold the fit pair's
+// transforms), correction solved with the existing factor.
+template <typename T>
+static hipError_t refine(Plan& pl, double* coef, hipStream_t st) {
+    const Geom& g = pl.g;
+    Workspace& w = pl.ws;
+    T* dfit = reinterpret_cast<T*>(w.dfit);
+    StageTimer t_(pl.prof, "refine", st);
+    Profiler* saved = pl.prof;
+    pl.prof = nullptr;   // inner stages count toward "refine"
+    struct Restore {
+        Plan& p;
+        Profiler* s;
+        ~Restore() { p.prof = s; }
+    } restore_{pl, saved};
+    const int dm = poly_degree(g);
+    hipError_t e = difference<T, T>(pl, g.dk + 1, true, coef, dfit, st);
+    if (!e) e = launch_polyrow<T>(g, dfit, 0, dm, g.w1, w.vrow, st);
+    if (!e) e = launch_polycorr(g, w.vrow, 0, dm, g.w0, g.w1, w.piD, st);
+    RowSources src{};
+    src.n = 1;
+    src.pow[0] = 0;
+    src.img[0] = 0;
+    src.out[0] = g.nr;
+    src.ped[0] = -1;
+    if (!e) e = launch_rowfwd<T, T>(g, pl.lp1, src, dfit, dfit, w.ped, cxp<T>(w.Z), cxp<T>(pl.t1.tw), st);
+    ColJobs jobs{};
+    jobs.narr = 1;
+    jobs.arr[0] = g.nr;
+    jobs.nw[0] = 1;
+    jobs.spec[0][0] = g.P + 1;
+    if (!e) e = launch_colfwd<T>(g, pl.lp0, jobs, cxp<T>(w.Z), cxp<T>(w.X), cxp<T>(pl.t0.tw), st);
+    if (!e) e = launch_lagcol<T>(g, pl.lp0, g.npair, g.nprod, g.P + 1, cxp<T>(w.X), cxp<T>(w.Cl), cxp<T>(pl.t0.tw), st);
+    if (!e) e = launch_lagrow<T>(g, g.npair, g.nprod, cxp<T>(w.Cl), pl.t1.twp, w.omega, w.thetaD, st);
+    if (!e) e = launch_lagfix(g, 1, w.ped, w.piR, w.piD, w.sig0, w.sig1, w.pw, dm, nullptr,
+                              w.thetaD, nullptr, nullptr, w.evecD, st);
+    if (!e) e = launch_gather(g, w.omega, w.thetaD, w.lam, w.cmat, w.evecD, nullptr, w.rhs, 1, st);
+    if (!e) e = launch_chol_solve(g.nu, w.L, w.dsc, w.rhs, coef, 1, w.flag, st);
+    return e;
+}
+
+template <typename T, typename Tin>
+static int run_build_t(Plan& pl, const void* r, const void* s, double* G, double* h, hipStream_t st) {
+    return hip_status(build<T, Tin>(pl, (const Tin*)r, (const Tin*)s, G, h, st));
+}
+
+template <typename T, typename Tin>
+static int run_solve_t(Plan& pl, const double* G, const double* h, const void* r, const void* s,
+                       double* coef, hipStream_t st) {
+    hipError_t e = launch_clear_flag(pl.ws.flag, st);
+    if (!e) e = factor_solve(pl, G, h, coef, st);
+    if (!e && pl.p.precision == SFFT_MIXED && r && s) {
+        e = poly_tables<Tin>(pl, (const Tin*)r, (const Tin*)s, st);
+        if (!e) e = forward_fit<T, Tin>(pl, (const Tin*)r, (const Tin*)s, st);
+        if (!e) e = refine<T>(pl, coef, st);
+    }
+    return hip_status(e);
+}
+
+template <typename T, typename Tin>
+static int run_subtract_t(Plan& pl, const void* r, const void* s, const double* coef, void* d,
+                          hipStream_t st) {
+    const Geom& g = pl.g;
+    hipError_t e;
+    {
+        StageTimer t_(pl.prof, "rowfwd", st);
+        e = launch_rowfwd<T, Tin>(g, pl.lp1, pair_sources(g, false), (const Tin*)r, (const Tin*)s,
+                                  nullptr, cxp<T>(pl.ws.Z), cxp<T>(pl.t1.tw), st);
+    }
+    if (!e) e = difference<T, Tin>(pl, g.dk + 1, false, coef, (Tin*)d, st);
+    return hip_status(e);
+}
+
+template <typename T, typename Tin>
+static int run_all_t(Plan& pl, const void* rf, const void* sf, const void* r, const void* s,
+                     double* coef, void* d, hipStream_t st) {
+    Workspace& w = pl.ws;
+    hipError_t e = launch_clear_flag(w.flag, st);
+    if (!e) e = build<T, Tin>(pl, (const Tin*)rf, (const Tin*)sf, w.G, w.h, st);
+    if (!e) e = factor_solve(pl, w.G, w.h, w.coef, st);
+    if (!e && pl.p.precision == SFFT_MIXED) e = refine<T>(pl, w.coef, st);
+    if (e) return hip_status(e);
+    if (coef) {
+        e = hipMemcpyAsync(coef, w.coef, pl.g.nu * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (e) return hip_status(e);
+    }
+    if (r == rf && s == sf) {
+        e = difference<T, Tin>(pl, pl.g.dk + 1, true, w.coef, (Tin*)d, st);
+        return hip_status(e);
+    }
+    return run_subtract_t<T, Tin>(pl, r, s, w.coef, d, st);
+}
+
+// Dispatch on (compute type, image type).
+#define SFFT_DISPATCH(pl, FN, ...)                                                        \
+    ((pl).p.precision == SFFT_MIXED                                                       \
+         ? ((pl).p.dtype == SFFT_F32 ? FN<float, float>(pl, __VA_ARGS__)                  \
+                                     : FN<float, double>(pl, __VA_ARGS__))                \
+         : ((pl).p.dtype == SFFT_F32 ? FN<double, float>(pl, __VA_ARGS__)                 \
+                                     : FN<double, double>(pl, __VA_ARGS__)))
+
+int plan_run(Plan& pl, const void* rf, const void* sf, const void* r, const void* s, double* coef,
+             void* d, hipStream_t st) {
+    return SFFT_DISPATCH(pl, run_all_t, rf, sf, r, s, coef, d, st);
+}
+
+int plan_read_flag(Plan& pl, hipStream_t st, int* flag) {
+    if (hipStreamSynchronize(st) != hipSuccess) return SFFT_E_HIP;
+    if (hipMemcpy(flag, pl.ws.flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SFFT_E_HIP;
+    return SFFT_OK;
+}
+
+int flag_status(int f) {
+    if (f & 2) return SFFT_E_NONFINITE;
+    if (f & 1) return SFFT_E_NOT_SPD;
+    return SFFT_OK;
+}
+
+}  // namespace sfft
+
+// ------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int sfft_create(sfft_ctx** out, int device, size_t hbm_budget_bytes) {
+    if (!out) return SFFT_E_INVAL;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SFFT_E_INVAL;
+    auto* c = new (std::nothrow) sfft_ctx();
+    if (!c) return SFFT_E_NOMEM;
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    *out = c;
+    return SFFT_OK;
+}
+
+void sfft_destroy(sfft_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->engine.reset();
+    for (auto& kv : ctx->plans) destroy_plan(ctx, kv.second);
+    for (auto& kv : ctx->twid) free_twiddles(kv.second);
+    delete ctx;
+}
+
+int64_t sfft_num_unknowns(const sfft_params* p) { return num_unknowns(p); }
+
+int sfft_check_params(const sfft_params* p) { return check_params(p); }
+
+int64_t sfft_workspace_bytes(const sfft_params* p) {
+    int rc = check_params(p);
+    if (rc) return rc;
+    return (int64_t)workspace_bytes(p);
+}
+
+int sfft_build_system(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void* s_fit,
+                      double* G, double* h, void* stream) {
+    if (!ctx || !r_fit || !s_fit || !G || !h) return SFFT_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    Plan* pl;
+    int rc = direct_plan(ctx, p, &pl);
+    if (rc) return rc;
+    return SFFT_DISPATCH(*pl, run_build_t, r_fit, s_fit, G, h, (hipStream_t)stream);
+}
+
+int sfft_solve(sfft_ctx* ctx, const sfft_params* p, const double* G, const double* h,
+               const void* r_fit, const void* s_fit, double* coef, void* stream) {
+    if (!ctx || !G || !h || !coef || ((r_fit == nullptr) != (s_fit == nullptr))) return SFFT_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    Plan* pl;
+    int rc = direct_plan(ctx, p, &pl);
+    if (rc) return rc;
+    rc = SFFT_DISPATCH(*pl, run_solve_t, G, h, r_fit, s_fit, coef, (hipStream_t)stream);
+    return rc;
+}
+
+int sfft_subtract(sfft_ctx* ctx, const sfft_params* p, const void* r, const void* s,
+                  const double* coef, void* d, void* stream) {
+    if (!ctx || !r || !s || !coef || !d) return SFFT_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    Plan* pl;
+    int rc = direct_plan(ctx, p, &pl);
+    if (rc) return rc;
+    return SFFT_DISPATCH(*pl, run_subtract_t, r, s, coef, d, (hipStream_t)stream);
+}
+
+int sfft_run(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void* s_fit,
+             const void* r, const void* s, double* coef, void* d, void* stream) {
+    if (!ctx || !r_fit || !s_fit || !r || !s || !d) return SFFT_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    Plan* pl;
+    int rc = direct_plan(ctx, p, &pl);
+    if (rc) return rc;
+    return plan_run(*pl, r_fit, s_fit, r, s, coef, d, (hipStream_t)stream);
+}
+
+int sfft_sync(sfft_ctx* ctx, void* stream) {
+    if (!ctx) return SFFT_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SFFT_E_HIP;
+    int all = 0;
+    for (auto& kv : ctx->plans) {
+        int f = 0;
+        if (hipMemcpy(&f, kv.second->ws.flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+            return SFFT_E_HIP;
+        all |= f;
+        if (f) (void)hipMemset(kv.second->ws.flag, 0, sizeof(int));
+    }
+    return flag_status(all);
+}
+
+int sfft_lag_tables(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void* s_fit,
+                    double* omega, double* theta, double* lambda, double* cmat, double* evec,
+                    void* stream) {
+    if (!ctx || !r_fit || !s_fit) return SFFT_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    Plan* pl;
+    int rc = direct_plan(ctx, p, &pl);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    auto run = [&](auto tag_t, auto tag_in) -> hipError_t {
+        using T = decltype(tag_t);
+        using Tin = decltype(tag_in);
+        return lag_tables<T, Tin>(*pl, (const Tin*)r_fit, (const Tin*)s_fit, st);
+    };
+    hipError_t e;
+    if (pl->p.precision == SFFT_MIXED)
+        e = pl->p.dtype == SFFT_F32 ? run(float{}, float{}) : run(float{}, double{});
+    else
+        e = pl->p.dtype == SFFT_F32 ? run(double{}, float{}) : run(double{}, double{});
+    if (e) return SFFT_E_HIP;
+    const Geom& g = pl->g;
+    Workspace& w = pl->ws;
+    auto cp = [&](double* dst, const double* src, size_t cnt) -> hipError_t {
+        return dst ? hipMemcpyAsync(dst, src, cnt * sizeof(double), hipMemcpyDeviceToDevice, st)
+                   : hipSuccess;
+    };
+    e = cp(omega, w.omega, (size_t)g.npair * g.D0 * g.D1);
+    if (!e) e = cp(theta, w.theta, (size_t)g.P * g.L0 * g.L1);
+    if (!e) e = cp(lambda, w.lam, (size_t)g.P * g.Q * g.L0 * g.L1);
+    if (!e) e = cp(cmat, w.cmat, (size_t)g.Q * g.Q);
+    if (!e) e = cp(evec, w.evec, (size_t)g.Q);
+    return hip_status(e);
+}
+
+int sfft_fft_lines(sfft_ctx* ctx, int n, int lines, int sign, int dtype, const void* in, void* out,
+                   void* stream) {
+    if (!ctx || !in || !out || lines < 0 || (sign != 1 && sign != -1)) return SFFT_E_INVAL;
+    int a, b;
+    if (n < 16 || n % 16 || n > 8192 || !radix23(n, &a, &b)) return SFFT_E_UNSUPPORTED;
+    if (dtype != SFFT_F32 && dtype != SFFT_F64) return SFFT_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    Twiddles t;
+    int rc = get_twiddles(ctx, n, dtype == SFFT_F32, &t);
+    if (rc) return rc;
+    LinePlan lp = make_line_plan(n);
+    hipError_t e;
+    if (dtype == SFFT_F32)
+        e = launch_fft_lines<float>(lp, lines, sign, (const cx<float>*)in, (cx<float>*)out,
+                                    (const cx<float>*)t.tw, (hipStream_t)stream);
+    else
+        e = launch_fft_lines<double>(lp, lines, sign, (const cx<double>*)in, (cx<double>*)out,
+                                     (const cx<double>*)t.tw, (hipStream_t)stream);
+    return hip_status(e);
+}
+
+int sfft_profile(sfft_ctx* ctx, int enable) {
+    if (!ctx) return SFFT_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& r : ctx->prof.recs) {
+        ctx->prof.pool.push_back(r.a);
+        ctx->prof.pool.push_back(r.b);
+    }
+    ctx->prof.recs.clear();
+    ctx->prof.on = enable != 0;
+    return SFFT_OK;
+}
+
+int sfft_profile_read(sfft_ctx* ctx, int max_stages, char* names, double* total_ms, int* counts) {
+    if (!ctx || max_stages < 0 || (max_stages && (!names || !total_ms || !counts))) return SFFT_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    if (hipDeviceSynchronize() != hipSuccess) return SFFT_E_HIP;
+    std::vector<std::string> order;
+    std::map<std::string, std::pair<double, int>> acc;
+    for (auto& r : ctx->prof.recs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return SFFT_E_HIP;
+        auto it = acc.find(r.name);
+        if (it == acc.end()) {
+            order.push_back(r.name);
+            acc[r.name] = {ms, 1};
+        } else {
+            it->second.first += ms;
+            it->second.second += 1;
+        }
+    }
+    const int n = (int)order.size();
+    for (int i = 0; i < n && i < max_stages; ++i) {
+        std::snprintf(names + 32 * i, 32, "%s", order[i].c_str());
+        total_ms[i] = acc[order[i]].first;
+        counts[i] = acc[order[i]].second;
+    }
+    return n;
+}
+
+const char* sfft_strerror(int s) {
+    switch (s) {
+        case SFFT_OK: return "ok";
+        case SFFT_PENDING: return "pending";
+        case SFFT_E_INVAL: return "invalid argument";
+        case SFFT_E_NOMEM: return "workspace exceeds the HBM budget or device memory";
+        case SFFT_E_NOT_SPD: return "normal matrix is not positive definite";
+        case SFFT_E_NONFINITE: return "non-finite value in the inputs or normal matrix";
+        case SFFT_E_UNSUPPORTED: return "unsupported size or parameter";
+        case SFFT_E_HIP: return "HIP runtime error";
+        case SFFT_E_NOTFOUND: return "unknown request ticket";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

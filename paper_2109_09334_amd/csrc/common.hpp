@@ -1,0 +1,122 @@
+// Shared types for the SFFT gfx950 library: geometry of one problem, FFT
+// line plans, complex arithmetic, launch helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sfft {
+
+// Complex number in a given real type, stored as (re, im) and aligned so a
+// single 64-bit (float) or 128-bit (double) access moves it.
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T re, im;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
+
+// Maximum number of radix passes of one line transform.
+constexpr int kMaxPass = 8;
+// Elements of one line held by one thread during a transform.
+constexpr int kElemsPerThread = 16;
+
+// Plan of one line length N = 2^a 3^b (multiple of 16): radix sequence and
+// the thread layout (TL threads per line, LPW lines per workgroup).
+struct LinePlan {
+    int n;
+    int npass;
+    int radix[kMaxPass];
+    int tl;     // threads per line = n / kElemsPerThread
+    int lpw;    // lines per workgroup
+};
+
+// Geometry of one subtraction problem (Eq. 1-6): image N0 x N1 (x = axis 0),
+// kernel half widths w0, w1, polynomial degrees DK (kernel) and DB
+// (background), ConstPhotRatio flag, and every derived count.
+struct Geom {
+    int n0, n1;
+    int h;        // N1/2 + 1: columns of a half spectrum along axis 1
+    int hp;       // padded row pitch (complex elements) of half-spectrum arrays
+    int w0, w1, dk, db, cp;
+    int P, Q;     // kernel / background polynomial term counts
+    int L0, L1;   // 2w+1
+    int nk, nu;   // kernel unknowns, all unknowns
+    int npair;    // P(P+1)/2 kernel-kernel correlation pairs
+    int nprod;    // npair + P spectral products per frequency
+    int nr;       // real rows fed to the row transform: DK+1 weighted R, and S
+    int D0, D1;   // 4w+1: lag range of the kernel-kernel tables
+};
+
+// Monomial index t -> exponents (i, j), i ascending then j ascending.
+__host__ __device__ __forceinline__ void term_ij(int deg, int t, int& i, int& j) {
+    int c = t;
+    for (int a = 0; a <= deg; ++a) {
+        int len = deg - a + 1;
+        if (c < len) { i = a; j = c; return; }
+        c -= len;
+    }
+    i = j = 0;
+}
+// (i, j) -> monomial index.
+__host__ __device__ __forceinline__ int term_index(int deg, int i, int j) {
+    int t = 0;
+    for (int a = 0; a < i; ++a) t += deg - a + 1;
+    return t + j;
+}
+
+// Centred, normalised coordinate c(x) = (2x - (N-1)) / (N-1).
+template <typename T>
+__host__ __device__ __forceinline__ T coord(int x, int n) {
+    return (T(2) * T(x) - T(n - 1)) / T(n - 1);
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ T ipow(T b, int e) {
+    T r = T(1);
+    for (int k = 0; k < e; ++k) r *= b;
+    return r;
+}
+
+__host__ __device__ __forceinline__ int imod(int a, int n) {
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// Kernel unknown u -> (k, a, b) in solver order (k, then a, then b, with the
+// (k>0, 0, 0) entries skipped under ConstPhotRatio).
+__host__ __device__ __forceinline__ void decode_unknown(const Geom& g, int u, int& k, int& a, int& b) {
+    int L = g.L0 * g.L1;
+    int rem;
+    if (!g.cp || u < L) {
+        k = u / L;
+        rem = u - k * L;
+    } else {
+        int up = u - L;
+        k = 1 + up / (L - 1);
+        rem = up - (k - 1) * (L - 1);
+        int centre = g.w0 * g.L1 + g.w1;
+        if (rem >= centre) rem += 1;
+    }
+    a = rem / g.L1 - g.w0;
+    b = rem % g.L1 - g.w1;
+}
+
+}  // namespace sfft

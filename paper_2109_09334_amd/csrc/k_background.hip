@@ -1,0 +1,314 @@
+// FP64 polynomial-correlation tables and the pedestal corrections of the
+// spectral lag tables.
+//
+// Poly-correlation of an image with monomials T^t = c0^i c1^j:
+//   Pi_{ta tb}(d) = sum_u img(u) T^ta(u) T^tb((u + d) mod N)
+// For img = R, ta = kb, tb = m this is Lambda_{kb m}(d) of Eq. B8; with
+// img = S, ta = 0 it holds E_m = Pi_{0 m}(0) (Eq. B15). Because T^tb is
+// separable, Pi = sum_u0 c0(u0)^ia c0((u0+d0) mod N0)^ib V_{ja jb}(u0, d1),
+//   V_{ja jb}(u0, d1) = sum_u1 img(u0,u1) c1(u1)^ja c1((u1+d1) mod N1)^jb,
+// and on the torus c1((u1+d1) mod N1) equals the straight-line value
+// c1(u1) + 2 d1/(N1-1) except on the |d1| wrapped columns, so V is a
+// binomial combination of the row moments M_e(u0) = sum_u1 img c1^e plus an
+// explicit correction over the wrapped columns.
+//
+// Pedestal: the spectral path transforms R' = R - c_R and S' = S - c_S
+// (c = image means) so that FP32 FFT rounding scales with the fluctuations
+// and not with the sky level. The exact identities restore the full tables:
+//   Omega_{kb k}(d) = Omega'(d) + c_R (Pi^R_{kb k}(d) + Pi^R_{k kb}(-d))
+//                     - c_R^2 C_{kb k}(d),  C(d) = sum_x T^kb(x-d) T^k(x)
+//   Theta_kb(d)     = Theta'(d) + c_S Pi^R_{kb 0}(0) + c_R Pi^S_{0 kb}(-d)
+//                     - c_R c_S sum_x T^kb
+// (expand R = R' + c_R, S = S' + c_S in Eq. B6, B14).
+#include "kernels.hpp"
+
+namespace sfft {
+
+constexpr int kMaxDeg = 4;
+constexpr int kMaxMom = 2 * kMaxDeg + 1;
+
+__device__ __forceinline__ double binom(int n, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum_bg(double* v, double* red) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double x = v[i];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        v[i] = x;
+    }
+    __syncthreads();
+    if (lane == 0)
+        for (int i = 0; i < NV; ++i) red[wv * NV + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[w * NV + threadIdx.x];
+        red[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// One row per block: V[u0][ja][jb][d1 + K1], ja <= da, jb <= db, |d1| <= K1.
+template <typename Tin>
+__global__ void __launch_bounds__(256) polyrow_kernel(Geom g, const Tin* __restrict__ img, int da,
+                                                      int dbb, int K1, double* __restrict__ vrow) {
+    __shared__ double red[4 * kMaxMom];
+    const int x0 = blockIdx.x;
+    const int n1 = g.n1;
+    const int ne = da + dbb + 1;
+    const Tin* row = img + (size_t)x0 * n1;
+    double mo[kMaxMom];
+#pragma unroll
+    for (int e = 0; e < kMaxMom; ++e) mo[e] = 0.0;
+    for (int x1 = threadIdx.x; x1 < n1; x1 += blockDim.x) {
+        const double c = coord<double>(x1, n1);
+        const double v = (double)row[x1];
+        double pw = 1.0;
+#pragma unroll
+        for (int e = 0; e < kMaxMom; ++e) {
+            if (e < ne) mo[e] += v * pw;
+            pw *= c;
+        }
+    }
+    block_sum_bg<kMaxMom>(mo, red);   // red[0..kMaxMom) = row moments
+    const int na = da + 1, nb = dbb + 1, nd = 2 * K1 + 1;
+    const double del = 2.0 / (double)(n1 - 1);
+    for (int idx = threadIdx.x; idx < na * nb * nd; idx += blockDim.x) {
+        const int ja = idx / (nb * nd);
+        const int jb = (idx / nd) % nb;
+        const int d1 = idx % nd - K1;
+        const double sh = del * (double)d1;
+        double v = 0.0;
+        for (int r = 0; r <= jb; ++r) v += binom(jb, r) * ipow(sh, jb - r) * red[ja + r];
+        const int lo = d1 > 0 ? n1 - d1 : 0, hi = d1 > 0 ? n1 : -d1;
+        for (int x1 = lo; x1 < hi; ++x1) {
+            const double c = coord<double>(x1, n1);
+            const double tor = coord<double>(imod(x1 + d1, n1), n1);
+            v += (double)row[x1] * ipow(c, ja) * (ipow(tor, jb) - ipow(c + sh, jb));
+        }
+        vrow[(size_t)x0 * na * nb * nd + idx] = v;
+    }
+}
+
+// Block (ta, tb, d0): Pi[ta][tb][d0 + K0][d1 + K1] for all |d1| <= K1.
+__global__ void __launch_bounds__(256) polycorr_kernel(Geom g, const double* __restrict__ vrow,
+                                                        int da, int dbb, int K0, int K1,
+                                                        double* __restrict__ pi) {
+    __shared__ double red[4 * 32];
+    const int n0 = g.n0;
+    const int nta = (da + 1) * (da + 2) / 2, ntb = (dbb + 1) * (dbb + 2) / 2;
+    const int nd0 = 2 * K0 + 1, nd1 = 2 * K1 + 1;
+    const int ta = blockIdx.x / (ntb * nd0);
+    const int tb = (blockIdx.x / nd0) % ntb;
+    const int d0 = blockIdx.x % nd0 - K0;
+    int ia, ja, ib, jb;
+    term_ij(da, ta, ia, ja);
+    term_ij(dbb, tb, ib, jb);
+    const int na = da + 1, nb = dbb + 1;
+    for (int base = 0; base < nd1; base += 32) {
+        double acc[32];
+#pragma unroll
+        for (int t = 0; t < 32; ++t) acc[t] = 0.0;
+        for (int x0 = threadIdx.x; x0 < n0; x0 += blockDim.x) {
+            const double wgt = ipow(coord<double>(x0, n0), ia) *
+                               ipow(coord<double>(imod(x0 + d0, n0), n0), ib);
+            const double* vr = vrow + (((size_t)x0 * na + ja) * nb + jb) * nd1;
+#pragma unroll
+            for (int t = 0; t < 32; ++t)
+                if (base + t < nd1) acc[t] += wgt * vr[base + t];
+        }
+        block_sum_bg<32>(acc, red);
+        if (threadIdx.x < 32 && base + threadIdx.x < nd1)
+            pi[(((size_t)ta * ntb + tb) * nd0 + d0 + K0) * nd1 + base + threadIdx.x] = red[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// 1-D sums sig0[ab][a][d0] = sum_x0 c0((x0-d0) mod N0)^ab c0(x0)^a (and the
+// same along axis 1), |d| <= 2w, exponents <= DK; pw0[e], pw1[e] = sum c^e
+// for e <= 2 max(DK, DB). One block per (axis, ab, a, d) or power.
+__global__ void __launch_bounds__(256) polysum_kernel(Geom g, int dmax, double* __restrict__ sig0,
+                                                       double* __restrict__ sig1,
+                                                       double* __restrict__ pw) {
+    __shared__ double red[4];
+    const int ne = g.dk + 1;
+    const int ns0 = ne * ne * g.D0, ns1 = ne * ne * g.D1;
+    int b = blockIdx.x;
+    int axis, ab = 0, a = 0, d = 0, e = 0;
+    bool power = false;
+    if (b < ns0) {
+        axis = 0;
+        ab = b / (ne * g.D0);
+        a = (b / g.D0) % ne;
+        d = b % g.D0 - 2 * g.w0;
+    } else if (b < ns0 + ns1) {
+        b -= ns0;
+        axis = 1;
+        ab = b / (ne * g.D1);
+        a = (b / g.D1) % ne;
+        d = b % g.D1 - 2 * g.w1;
+    } else {
+        b -= ns0 + ns1;
+        power = true;
+        axis = b / (2 * dmax + 1);
+        e = b % (2 * dmax + 1);
+    }
+    const int n = axis ? g.n1 : g.n0;
+    double acc = 0.0;
+    for (int x = threadIdx.x; x < n; x += blockDim.x) {
+        const double c = coord<double>(x, n);
+        acc += power ? ipow(c, e) : ipow(coord<double>(imod(x - d, n), n), ab) * ipow(c, a);
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+        if (power) pw[axis * (2 * dmax + 1) + e] = s;
+        else if (axis == 0) sig0[(ab * ne + a) * g.D0 + d + 2 * g.w0] = s;
+        else sig1[(ab * ne + a) * g.D1 + d + 2 * g.w1] = s;
+    }
+}
+
+// Pedestals: image means from the (0, 0) entries of the poly tables.
+__global__ void pedestal_kernel(Geom g, const double* __restrict__ piR, int ntbR, int K0R, int K1R,
+                                const double* __restrict__ piS, int ntbS, int K0S, int K1S,
+                                double* __restrict__ ped) {
+    (void)ntbR;
+    (void)ntbS;
+    const double n = (double)g.n0 * (double)g.n1;
+    ped[0] = piR[(size_t)K0R * (2 * K1R + 1) + K1R] / n;
+    ped[1] = piS[(size_t)K0S * (2 * K1S + 1) + K1S] / n;
+}
+
+// Assemble the FP64 tables used by the gather:
+//  mode 0 (build): Omega, Theta += pedestal corrections; Lambda, E, C written.
+//  mode 1 (refinement): Theta (of the difference image) += correction; E.
+__global__ void __launch_bounds__(256) lagfix_kernel(Geom g, int mode, const double* __restrict__ ped,
+                                                      const double* __restrict__ piR,
+                                                      const double* __restrict__ piS,
+                                                      const double* __restrict__ sig0,
+                                                      const double* __restrict__ sig1,
+                                                      const double* __restrict__ pw, int dmax,
+                                                      double* __restrict__ omega,
+                                                      double* __restrict__ theta,
+                                                      double* __restrict__ lam,
+                                                      double* __restrict__ cmat,
+                                                      double* __restrict__ evec) {
+    const double cR = ped[0], cS = mode == 0 ? ped[1] : 0.0;
+    const int ntb = (dmax + 1) * (dmax + 2) / 2;
+    const int ne = g.dk + 1;
+    // Pi^R layout [P][ntb][4w0+1][4w1+1]; Pi^S (and Pi^D) layout [ntb][2w0+1][2w1+1]
+    auto piR_at = [&](int ta, int tb, int d0, int d1) {
+        return piR[(((size_t)ta * ntb + tb) * g.D0 + d0 + 2 * g.w0) * g.D1 + d1 + 2 * g.w1];
+    };
+    auto piS_at = [&](int tb, int d0, int d1) {
+        return piS[((size_t)tb * g.L0 + d0 + g.w0) * g.L1 + d1 + g.w1];
+    };
+    auto tsum = [&](int i, int j) {   // sum_x T^(i,j)
+        return pw[i] * pw[(2 * dmax + 1) + j];
+    };
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nth = gridDim.x * blockDim.x;
+    // Theta (both modes)
+    for (int idx = tid; idx < g.P * g.L0 * g.L1; idx += nth) {
+        const int kb = idx / (g.L0 * g.L1);
+        const int d0 = (idx / g.L1) % g.L0 - g.w0, d1 = idx % g.L1 - g.w1;
+        int ib, jb;
+        term_ij(g.dk, kb, ib, jb);
+        const int tbk = term_index(dmax, ib, jb);
+        double v = cR * piS_at(tbk, -d0, -d1);
+        if (mode == 0) v += cS * piR_at(kb, 0, 0, 0) - cR * cS * tsum(ib, jb);
+        theta[idx] += v;
+    }
+    for (int m = tid; m < g.Q; m += nth) {
+        int p, q;
+        term_ij(g.db, m, p, q);
+        evec[m] = piS_at(term_index(dmax, p, q), 0, 0);
+    }
+    if (mode != 0) return;
+    for (int idx = tid; idx < g.npair * g.D0 * g.D1; idx += nth) {
+        const int pr = idx / (g.D0 * g.D1);
+        const int d0 = (idx / g.D1) % g.D0 - 2 * g.w0, d1 = idx % g.D1 - 2 * g.w1;
+        int kb = 0, c = pr;
+        while (c >= g.P - kb) { c -= g.P - kb; ++kb; }
+        const int k = kb + c;
+        int ib, jb, i, j;
+        term_ij(g.dk, kb, ib, jb);
+        term_ij(g.dk, k, i, j);
+        const double Cd = sig0[(ib * ne + i) * g.D0 + d0 + 2 * g.w0] *
+                          sig1[(jb * ne + j) * g.D1 + d1 + 2 * g.w1];
+        const double v = cR * (piR_at(kb, term_index(dmax, i, j), d0, d1) +
+                               piR_at(k, term_index(dmax, ib, jb), -d0, -d1)) -
+                         cR * cR * Cd;
+        omega[idx] += v;
+    }
+    for (int idx = tid; idx < g.P * g.Q * g.L0 * g.L1; idx += nth) {
+        const int kb = idx / (g.Q * g.L0 * g.L1);
+        const int m = (idx / (g.L0 * g.L1)) % g.Q;
+        const int d0 = (idx / g.L1) % g.L0 - g.w0, d1 = idx % g.L1 - g.w1;
+        int p, q;
+        term_ij(g.db, m, p, q);
+        lam[idx] = piR_at(kb, term_index(dmax, p, q), d0, d1);
+    }
+    for (int idx = tid; idx < g.Q * g.Q; idx += nth) {
+        int pb, qb, p, q;
+        term_ij(g.db, idx / g.Q, pb, qb);
+        term_ij(g.db, idx % g.Q, p, q);
+        cmat[idx] = pw[pb + p] * pw[(2 * dmax + 1) + qb + q];
+    }
+}
+
+template <typename Tin>
+hipError_t launch_polyrow(const Geom& g, const Tin* img, int da, int dbb, int K1, double* vrow,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(polyrow_kernel<Tin>, dim3(g.n0), dim3(256), 0, st, g, img, da, dbb, K1, vrow);
+    return hipGetLastError();
+}
+
+hipError_t launch_polycorr(const Geom& g, const double* vrow, int da, int dbb, int K0, int K1,
+                           double* pi, hipStream_t st) {
+    const int nta = (da + 1) * (da + 2) / 2, ntb = (dbb + 1) * (dbb + 2) / 2;
+    hipLaunchKernelGGL(polycorr_kernel, dim3(nta * ntb * (2 * K0 + 1)), dim3(256), 0, st, g, vrow,
+                       da, dbb, K0, K1, pi);
+    return hipGetLastError();
+}
+
+hipError_t launch_polysum(const Geom& g, int dmax, double* sig0, double* sig1, double* pw,
+                          hipStream_t st) {
+    const int ne = g.dk + 1;
+    const int nb = ne * ne * (g.D0 + g.D1) + 2 * (2 * dmax + 1);
+    hipLaunchKernelGGL(polysum_kernel, dim3(nb), dim3(256), 0, st, g, dmax, sig0, sig1, pw);
+    return hipGetLastError();
+}
+
+hipError_t launch_pedestal(const Geom& g, const double* piR, int dmax, const double* piS,
+                           double* ped, hipStream_t st) {
+    const int ntb = (dmax + 1) * (dmax + 2) / 2;
+    hipLaunchKernelGGL(pedestal_kernel, dim3(1), dim3(1), 0, st, g, piR, ntb, 2 * g.w0, 2 * g.w1,
+                       piS, ntb, g.w0, g.w1, ped);
+    return hipGetLastError();
+}
+
+hipError_t launch_lagfix(const Geom& g, int mode, const double* ped, const double* piR,
+                         const double* piS, const double* sig0, const double* sig1,
+                         const double* pw, int dmax, double* omega, double* theta, double* lam,
+                         double* cmat, double* evec, hipStream_t st) {
+    hipLaunchKernelGGL(lagfix_kernel, dim3(64), dim3(256), 0, st, g, mode, ped, piR, piS, sig0, sig1,
+                       pw, dmax, omega, theta, lam, cmat, evec);
+    return hipGetLastError();
+}
+
+template hipError_t launch_polyrow<float>(const Geom&, const float*, int, int, int, double*,
+                                          hipStream_t);
+template hipError_t launch_polyrow<double>(const Geom&, const double*, int, int, int, double*,
+                                           hipStream_t);
+
+}  // namespace sfft

@@ -1,0 +1,269 @@
+// Forward / inverse line-transform passes of the SFFT hot path.
+//
+// Row pass (axis 1, contiguous): the y-coordinate weights of Eq. 6 and Eq. 2
+// vary along the transformed axis, so they are applied on load; two real
+// rows are packed as one complex line and separated after the transform
+// into half spectra (m = 0 .. N1/2).
+// Column pass (axis 0): the x-coordinate weights are per-row scalars of the
+// row spectra, applied on load, so DK+2 row transforms feed all (DK+1)(DK+2)/2
+// weighted spectra of R plus the spectrum of S (Eq. 13, App. B).
+#include "fft_engine.hpp"
+#include "kernels.hpp"
+
+namespace sfft {
+
+template <typename T>
+__device__ __forceinline__ cx<T>* lds_base() {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    return reinterpret_cast<cx<T>*>(smem_raw);
+}
+
+template <typename T, typename Tin>
+__global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSources src,
+                                                      const Tin* __restrict__ img0,
+                                                      const Tin* __restrict__ img1,
+                                                      const double* __restrict__ ped,
+                                                      cx<T>* __restrict__ Z,
+                                                      const cx<T>* __restrict__ tw) {
+    cx<T>* lds = lds_base<T>();
+    const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
+    const int row = blockIdx.x * lp.lpw + line;
+    const bool act = row < g.n0;
+    const int n1 = g.n1;
+    cx<T>* buf = lds + line * lp.n;
+    const int npk = (src.n + 1) / 2;
+    for (int pk = 0; pk < npk; ++pk) {
+        const int ia = 2 * pk, ib = 2 * pk + 1;
+        const bool hasb = ib < src.n;
+        if (act) {
+            const Tin* pa = (src.img[ia] ? img1 : img0) + (size_t)row * n1;
+            const Tin* pb = (hasb && src.img[ib] ? img1 : img0) + (size_t)row * n1;
+            const int ea = src.pow[ia], eb = hasb ? src.pow[ib] : 0;
+            const double qa = src.ped[ia] >= 0 ? ped[src.ped[ia]] : 0.0;
+            const double qb = hasb && src.ped[ib] >= 0 ? ped[src.ped[ib]] : 0.0;
+#pragma unroll
+            for (int e = 0; e < kElemsPerThread; ++e) {
+                const int x1 = lt + e * lp.tl;
+                const T c = coord<T>(x1, n1);
+                const T va = ipow(c, ea) * T((double)pa[x1] - qa);
+                const T vb = hasb ? ipow(c, eb) * T((double)pb[x1] - qb) : T(0);
+                buf[x1] = mk(va, vb);
+            }
+        }
+        __syncthreads();
+        line_fft<-1, T>(buf, lp, lt, tw);
+        if (act) {
+            cx<T>* za = Z + ((size_t)src.out[ia] * g.n0 + row) * g.hp;
+            cx<T>* zb = Z + ((size_t)(hasb ? src.out[ib] : 0) * g.n0 + row) * g.hp;
+            for (int m = lt; m < g.h; m += lp.tl) {
+                const cx<T> a = buf[m], b = buf[m == 0 ? 0 : n1 - m];
+                za[m] = mk((a.re + b.re) * T(0.5), (a.im - b.im) * T(0.5));
+                if (hasb) zb[m] = mk((a.im + b.im) * T(0.5), (b.re - a.re) * T(0.5));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJobs jobs,
+                                                      const cx<T>* __restrict__ Z,
+                                                      cx<T>* __restrict__ X,
+                                                      const cx<T>* __restrict__ tw) {
+    cx<T>* lds = lds_base<T>();
+    const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
+    const int m = blockIdx.x * lp.lpw + line;
+    const bool act = m < g.h;
+    const int n0 = g.n0;
+    const int job = blockIdx.y;
+    const int a = jobs.arr[job];
+    cx<T>* buf = lds + line * lp.n;
+    cx<T> z[kElemsPerThread];
+    if (act) {
+        const cx<T>* zc = Z + (size_t)a * n0 * g.hp + m;
+#pragma unroll
+        for (int e = 0; e < kElemsPerThread; ++e) z[e] = zc[(size_t)(lt + e * lp.tl) * g.hp];
+    }
+    const int nw = jobs.nw[job];
+    for (int i = 0; i < nw; ++i) {
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < kElemsPerThread; ++e) {
+                const int x0 = lt + e * lp.tl;
+                buf[x0] = cscale(z[e], ipow(coord<T>(x0, n0), i));
+            }
+        }
+        __syncthreads();
+        line_fft<-1, T>(buf, lp, lt, tw);
+        if (act) {
+            cx<T>* xo = X + ((size_t)jobs.spec[job][i] * g.h + m) * n0;
+#pragma unroll
+            for (int e = 0; e < kElemsPerThread; ++e) {
+                const int l = lt + e * lp.tl;
+                xo[l] = buf[l];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// D(x0, .) = (1/N1) IDFT_row[Dt(x0, .)] - B(x0, .): two rows per packed
+// complex line (Hermitian extension of each half spectrum).
+template <typename T, typename Tout>
+__global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
+                                                      const cx<T>* __restrict__ Dt,
+                                                      Tout* __restrict__ d,
+                                                      const double* __restrict__ bcoef,
+                                                      const cx<T>* __restrict__ tw) {
+    cx<T>* lds = lds_base<T>();
+    const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
+    const int pr = blockIdx.x * lp.lpw + line;
+    const int xa = 2 * pr, xb = 2 * pr + 1;
+    const bool act = xb < g.n0;
+    const int n1 = g.n1;
+    cx<T>* buf = lds + line * lp.n;
+    if (act) {
+        const cx<T>* A = Dt + (size_t)xa * g.hp;
+        const cx<T>* B = Dt + (size_t)xb * g.hp;
+#pragma unroll
+        for (int e = 0; e < kElemsPerThread; ++e) {
+            const int m = lt + e * lp.tl;
+            cx<T> a, b;
+            if (m < g.h) {
+                a = A[m];
+                b = B[m];
+                if (m == 0 || 2 * m == n1) { a.im = T(0); b.im = T(0); }
+            } else {
+                a = cconj(A[n1 - m]);
+                b = cconj(B[n1 - m]);
+            }
+            buf[m] = mk(a.re - b.im, a.im + b.re);
+        }
+    }
+    __syncthreads();
+    line_fft<1, T>(buf, lp, lt, tw);
+    if (act) {
+        const double inv = 1.0 / (double)n1;
+        const double ca = coord<double>(xa, g.n0), cb = coord<double>(xb, g.n0);
+#pragma unroll
+        for (int e = 0; e < kElemsPerThread; ++e) {
+            const int x1 = lt + e * lp.tl;
+            const double c1 = coord<double>(x1, n1);
+            double ba = 0.0, bb = 0.0;
+            for (int m = 0; m < g.Q; ++m) {
+                int p, q;
+                term_ij(g.db, m, p, q);
+                const double t = bcoef[m] * ipow(c1, q);
+                ba += t * ipow(ca, p);
+                bb += t * ipow(cb, p);
+            }
+            const cx<T> v = buf[x1];
+            d[(size_t)xa * n1 + x1] = Tout((double)v.re * inv - ba);
+            d[(size_t)xb * n1 + x1] = Tout((double)v.im * inv - bb);
+        }
+    }
+}
+
+template <typename T, int S>
+__global__ void __launch_bounds__(512) fft_lines_kernel(LinePlan lp, int nlines,
+                                                         const cx<T>* __restrict__ in,
+                                                         cx<T>* __restrict__ out,
+                                                         const cx<T>* __restrict__ tw) {
+    cx<T>* lds = lds_base<T>();
+    const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
+    const int ln = blockIdx.x * lp.lpw + line;
+    const bool act = ln < nlines;
+    cx<T>* buf = lds + line * lp.n;
+    if (act)
+        for (int e = 0; e < kElemsPerThread; ++e) buf[lt + e * lp.tl] = in[(size_t)ln * lp.n + lt + e * lp.tl];
+    __syncthreads();
+    line_fft<S, T>(buf, lp, lt, tw);
+    if (act)
+        for (int e = 0; e < kElemsPerThread; ++e) out[(size_t)ln * lp.n + lt + e * lp.tl] = buf[lt + e * lp.tl];
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <typename K>
+static hipError_t set_lds(K kern, size_t bytes) {
+    if (bytes > 65536)
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return hipSuccess;
+}
+
+template <typename T, typename Tin>
+hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& src, const Tin* img0,
+                         const Tin* img1, const double* ped, cx<T>* Z, const cx<T>* tw,
+                         hipStream_t st) {
+    const size_t lds = (size_t)lp.lpw * lp.n * sizeof(cx<T>);
+    auto k = rowfwd_kernel<T, Tin>;
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((g.n0 + lp.lpw - 1) / lp.lpw);
+    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, src, img0, img1, ped, Z, tw);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs, const cx<T>* Z,
+                         cx<T>* X, const cx<T>* tw, hipStream_t st) {
+    const size_t lds = (size_t)lp.lpw * lp.n * sizeof(cx<T>);
+    auto k = colfwd_kernel<T>;
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((g.h + lp.lpw - 1) / lp.lpw, jobs.narr);
+    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, jobs, Z, X, tw);
+    return hipGetLastError();
+}
+
+template <typename T, typename Tout>
+hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, Tout* d,
+                         const double* bcoef, const cx<T>* tw, hipStream_t st) {
+    const size_t lds = (size_t)lp.lpw * lp.n * sizeof(cx<T>);
+    auto k = rowinv_kernel<T, Tout>;
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((g.n0 / 2 + lp.lpw - 1) / lp.lpw);
+    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, Dt, d, bcoef, tw);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_lines(const LinePlan& lp, int nlines, int sign, const cx<T>* in, cx<T>* out,
+                            const cx<T>* tw, hipStream_t st) {
+    const size_t lds = (size_t)lp.lpw * lp.n * sizeof(cx<T>);
+    dim3 grid((nlines + lp.lpw - 1) / lp.lpw);
+    if (sign < 0) {
+        auto k = fft_lines_kernel<T, -1>;
+        hipError_t e = set_lds(k, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, lp, nlines, in, out, tw);
+    } else {
+        auto k = fft_lines_kernel<T, 1>;
+        hipError_t e = set_lds(k, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, lp, nlines, in, out, tw);
+    }
+    return hipGetLastError();
+}
+
+#define SFFT_INST_T(T)                                                                            \
+    template hipError_t launch_colfwd<T>(const Geom&, const LinePlan&, const ColJobs&,            \
+                                         const cx<T>*, cx<T>*, const cx<T>*, hipStream_t);         \
+    template hipError_t launch_fft_lines<T>(const LinePlan&, int, int, const cx<T>*, cx<T>*,      \
+                                            const cx<T>*, hipStream_t);
+SFFT_INST_T(float)
+SFFT_INST_T(double)
+#define SFFT_INST_TT(T, U)                                                                        \
+    template hipError_t launch_rowfwd<T, U>(const Geom&, const LinePlan&, const RowSources&,      \
+                                            const U*, const U*, const double*, cx<T>*,            \
+                                            const cx<T>*, hipStream_t);                           \
+    template hipError_t launch_rowinv<T, U>(const Geom&, const LinePlan&, const cx<T>*, U*,       \
+                                            const double*, const cx<T>*, hipStream_t);
+SFFT_INST_TT(float, float)
+SFFT_INST_TT(float, double)
+SFFT_INST_TT(double, float)
+SFFT_INST_TT(double, double)
+
+}  // namespace sfft

@@ -1,0 +1,159 @@
+// Difference image D = S - sum_k R^k o kappa_k - B (Eq. 12-13).
+//
+// Stamps: kappa_k(a) = c_(k,a) for a != 0 and kappa_k(0) = c_(k,0) minus the
+// off-centre sum (delta basis of Eq. 3-4). The convolution runs spectrally
+// along axis 1 and directly along axis 0: with the row spectra
+// Z_j(x0, m) = DFT_row[c1^j R](x0, m), the shift by a1 is the factor
+// W_N1^(m a1) of Eq. 14, so
+//   Dt(x0, m) = Z_S(x0, m) - sum_j sum_a0 Z_j(x0 - a0, m)
+//               sum_i Kt_(i,j)(a0, m) c0(x0 - a0)^i,
+//   Kt_k(a0, m) = sum_a1 kappa_k(a0, a1) W_N1^(m a1),
+// a (2 w0 + 1)-tap stencil along x0 per column m; the row inverse (k_fft)
+// then gives D and subtracts the background polynomial.
+#include "kernels.hpp"
+
+namespace sfft {
+
+// Coefficient index of kernel unknown (k, a, b), or -1 when it is fixed
+// (ConstPhotRatio centre entries of k > 0).
+__device__ __forceinline__ int coef_index(const Geom& g, int k, int a, int b) {
+    const int L = g.L0 * g.L1;
+    int rem = (a + g.w0) * g.L1 + (b + g.w1);
+    if (!g.cp) return k * L + rem;
+    if (k == 0) return rem;
+    const int centre = g.w0 * g.L1 + g.w1;
+    if (rem == centre) return -1;
+    if (rem > centre) rem -= 1;
+    return L + (k - 1) * (L - 1) + rem;
+}
+
+__global__ void __launch_bounds__(256) stamps_kernel(Geom g, const double* __restrict__ coef,
+                                                      double* __restrict__ kap) {
+    __shared__ double red[4];
+    const int k = blockIdx.x;
+    const int L = g.L0 * g.L1;
+    double off = 0.0;
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+        const int a = t / g.L1 - g.w0, b = t % g.L1 - g.w1;
+        const int ci = coef_index(g, k, a, b);
+        const double c = ci >= 0 ? coef[ci] : 0.0;
+        kap[(size_t)k * L + t] = c;
+        if (a || b) off += c;
+    }
+    for (int o = 32; o > 0; o >>= 1) off += __shfl_down(off, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = off;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+        const int ci = coef_index(g, k, 0, 0);
+        kap[(size_t)k * L + g.w0 * g.L1 + g.w1] = (ci >= 0 ? coef[ci] : 0.0) - s;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) stamp_spectra_kernel(Geom g, const double* __restrict__ kap,
+                                                             const double* __restrict__ twp,
+                                                             cx<T>* __restrict__ Kt) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y;   // k * L0 + a0 index
+    if (m >= g.h) return;
+    const double* kr = kap + (size_t)row * g.L1;
+    double re = 0.0, im = 0.0;
+    for (int b = -g.w1; b <= g.w1; ++b) {
+        const int idx = imod(m * b, g.n1);
+        // W^(m b) = e^(-2 pi i m b / N1) = conj(twp[idx])
+        re += kr[b + g.w1] * twp[2 * idx];
+        im -= kr[b + g.w1] * twp[2 * idx + 1];
+    }
+    Kt[(size_t)row * g.hp + m] = mk(T(re), T(im));
+}
+
+// Row spectra of the weights: Y_j(m) = sum_x1 c1(x1)^j W_N1^(m x1), so the
+// row spectrum of c1^j (R' + c_R) is Z'_j + c_R Y_j (and Y_0 = N1 delta_m0).
+__global__ void __launch_bounds__(256) ytab_kernel(Geom g, const double* __restrict__ twp,
+                                                    cx<double>* __restrict__ ytab) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (m >= g.h) return;
+    double re = 0.0, im = 0.0;
+    for (int x1 = 0; x1 < g.n1; ++x1) {
+        const double c = ipow(coord<double>(x1, g.n1), j);
+        const int idx = (int)(((long long)m * x1) % g.n1);
+        re += c * twp[2 * idx];
+        im -= c * twp[2 * idx + 1];
+    }
+    ytab[(size_t)j * g.h + m] = cx<double>{re, im};
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) stencil_kernel(Geom g, const cx<T>* __restrict__ Z, int zs,
+                                                       const cx<T>* __restrict__ Kt,
+                                                       const double* __restrict__ ped,
+                                                       const cx<double>* __restrict__ ytab,
+                                                       cx<T>* __restrict__ Dt) {
+    const int m = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int x0 = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (m >= g.h || x0 >= g.n0) return;
+    const int n0 = g.n0;
+    const size_t plane = (size_t)n0 * g.hp;
+    cx<T> acc = Z[(size_t)zs * plane + (size_t)x0 * g.hp + m];
+    const double cR = ped ? ped[0] : 0.0;
+    if (ped && m == 0) acc.re += T(ped[1] * (double)g.n1);
+    for (int j = 0; j <= g.dk; ++j) {
+        const cx<T>* Zj = Z + (size_t)j * plane + m;
+        const cx<double> y = ped ? ytab[(size_t)j * g.h + m] : cx<double>{0.0, 0.0};
+        const cx<T> add = mk(T(cR * y.re), T(cR * y.im));
+        for (int a0 = -g.w0; a0 <= g.w0; ++a0) {
+            const int xs = imod(x0 - a0, n0);
+            const cx<T> z = Zj[(size_t)xs * g.hp] + add;
+            const T c = coord<T>(xs, n0);
+            // Horner over i = DK-j .. 0 of Kt_(i,j)(a0, m) c^i
+            cx<T> poly = mk(T(0), T(0));
+            for (int i = g.dk - j; i >= 0; --i) {
+                const cx<T> kt = Kt[((size_t)term_index(g.dk, i, j) * g.L0 + a0 + g.w0) * g.hp + m];
+                poly = mk(poly.re * c + kt.re, poly.im * c + kt.im);
+            }
+            acc = acc - cmul(poly, z);
+        }
+    }
+    Dt[(size_t)x0 * g.hp + m] = acc;
+}
+
+hipError_t launch_stamps(const Geom& g, const double* coef, double* kap, hipStream_t st) {
+    hipLaunchKernelGGL(stamps_kernel, dim3(g.P), dim3(256), 0, st, g, coef, kap);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stamp_spectra(const Geom& g, const double* kap, const double* twp, cx<T>* Kt,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(stamp_spectra_kernel<T>, dim3((g.h + 255) / 256, g.P * g.L0), dim3(256), 0,
+                       st, g, kap, twp, Kt);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<T>* Kt,
+                          const double* ped, const cx<double>* ytab, cx<T>* Dt, hipStream_t st) {
+    hipLaunchKernelGGL(stencil_kernel<T>, dim3((g.h + 63) / 64, (g.n0 + 3) / 4), dim3(256), 0, st,
+                       g, Z, zs_index, Kt, ped, ytab, Dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_ytab(const Geom& g, const double* twp, cx<double>* ytab, hipStream_t st) {
+    hipLaunchKernelGGL(ytab_kernel, dim3((g.h + 255) / 256, g.dk + 1), dim3(256), 0, st, g, twp, ytab);
+    return hipGetLastError();
+}
+
+template hipError_t launch_stamp_spectra<float>(const Geom&, const double*, const double*,
+                                                cx<float>*, hipStream_t);
+template hipError_t launch_stamp_spectra<double>(const Geom&, const double*, const double*,
+                                                 cx<double>*, hipStream_t);
+template hipError_t launch_stencil<float>(const Geom&, const cx<float>*, int, const cx<float>*,
+                                          const double*, const cx<double>*, cx<float>*, hipStream_t);
+template hipError_t launch_stencil<double>(const Geom&, const cx<double>*, int, const cx<double>*,
+                                           const double*, const cx<double>*, cx<double>*,
+                                           hipStream_t);
+
+}  // namespace sfft

@@ -1,0 +1,93 @@
+// Host-side launchers of the gfx950 kernels. Every launcher enqueues on the
+// given stream and returns the hipError_t of the launch.
+#pragma once
+#include "common.hpp"
+
+namespace sfft {
+
+// Up to kMaxSrc real rows can be fed to one row transform: row source s is
+// c1(y)^pow[s] * img[s] (img is R or S of the pair, or an intermediate).
+constexpr int kMaxSrc = 10;
+struct RowSources {
+    int n;                    // number of real sources (output arrays)
+    int pow[kMaxSrc];         // exponent of the y-coordinate weight
+    int img[kMaxSrc];         // 0 -> first image pointer, 1 -> second
+    int out[kMaxSrc];         // output array index in Z
+    int ped[kMaxSrc];         // index into the pedestal vector subtracted on load, -1: none
+};
+
+// Column-transform jobs: input array a of Z produces spectra for x-weight
+// exponents i = 0 .. nw[a]-1, written to spectrum index first[a] + i ... as
+// given by spec[a][i].
+constexpr int kMaxArr = 8;
+constexpr int kMaxW = 8;
+struct ColJobs {
+    int narr;
+    int arr[kMaxArr];             // Z array index
+    int nw[kMaxArr];              // number of weights
+    int spec[kMaxArr][kMaxW];     // output spectrum index for weight i
+};
+
+template <typename T, typename Tin>
+hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& src, const Tin* img0,
+                         const Tin* img1, const double* ped, cx<T>* Z, const cx<T>* tw,
+                         hipStream_t st);
+template <typename T>
+hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs, const cx<T>* Z,
+                         cx<T>* X, const cx<T>* tw, hipStream_t st);
+template <typename T, typename Tout>
+hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, Tout* d,
+                         const double* bcoef, const cx<T>* tw, hipStream_t st);
+template <typename T>
+hipError_t launch_fft_lines(const LinePlan& lp, int nlines, int sign, const cx<T>* in, cx<T>* out,
+                            const cx<T>* tw, hipStream_t st);
+
+// Products conj(X[kb]) X[k] for products p in [p0, p1): pairs kb <= k of the
+// kernel spectra (p < npair) then (kb, S-slot) with the S spectrum at
+// index sslot. Pruned inverse along axis 0 kept for |d0| <= lag range.
+template <typename T>
+hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int sslot,
+                         const cx<T>* X, cx<T>* Cl, const cx<T>* tw, hipStream_t st);
+template <typename T>
+hipError_t launch_lagrow(const Geom& g, int p0, int p1, const cx<T>* Cl, const double* twp,
+                         double* omega, double* theta, hipStream_t st);
+
+// FP64 polynomial-correlation tables and pedestal corrections (k_background).
+template <typename Tin>
+hipError_t launch_polyrow(const Geom& g, const Tin* img, int da, int dbb, int K1, double* vrow,
+                          hipStream_t st);
+hipError_t launch_polycorr(const Geom& g, const double* vrow, int da, int dbb, int K0, int K1,
+                           double* pi, hipStream_t st);
+hipError_t launch_polysum(const Geom& g, int dmax, double* sig0, double* sig1, double* pw,
+                          hipStream_t st);
+hipError_t launch_pedestal(const Geom& g, const double* piR, int dmax, const double* piS,
+                           double* ped, hipStream_t st);
+hipError_t launch_lagfix(const Geom& g, int mode, const double* ped, const double* piR,
+                         const double* piS, const double* sig0, const double* sig1,
+                         const double* pw, int dmax, double* omega, double* theta, double* lam,
+                         double* cmat, double* evec, hipStream_t st);
+hipError_t launch_gather(const Geom& g, const double* om, const double* th, const double* la,
+                         const double* cm, const double* ev, double* G, double* h, int rhs_only,
+                         hipStream_t st);
+
+// Cholesky of the Jacobi-scaled normal matrix and triangular solves.
+hipError_t launch_jacobi(int n, const double* G, const double* h, double* L, double* dsc,
+                         double* rhs, int* flag, hipStream_t st);
+hipError_t launch_cholesky(int n, double* L, int* flag, hipStream_t st);
+hipError_t launch_chol_solve(int n, const double* L, const double* dsc, double* rhs,
+                             double* coef, int accumulate, const int* flag, hipStream_t st);
+hipError_t launch_clear_flag(int* flag, hipStream_t st);
+
+// Subtraction.
+hipError_t launch_stamps(const Geom& g, const double* coef, double* kap, hipStream_t st);
+template <typename T>
+hipError_t launch_stamp_spectra(const Geom& g, const double* kap, const double* twp, cx<T>* Kt,
+                                hipStream_t st);
+// ped (nullable): pedestals (c_R, c_S) removed from the row spectra in Z;
+// ytab: row spectra of the weights c1^j, [DK+1][h] FP64 complex.
+template <typename T>
+hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<T>* Kt,
+                          const double* ped, const cx<double>* ytab, cx<T>* Dt, hipStream_t st);
+hipError_t launch_ytab(const Geom& g, const double* twp, cx<double>* ytab, hipStream_t st);
+
+}  // namespace sfft

@@ -281,3 +281,12 @@ def test_pixel_route_and_kernel_sum_field():
     c1 = (2.0 * np.arange(26) - 25) / 25
     ref = sum(kap[k].sum() * c0[:, None] ** i * c1[None, :] ** j for k, (i, j) in enumerate(oracle.terms(2)))
     assert np.abs(ks - ref).max() < 1e-12
+
+
+def test_phi_dot_is_a_column_of_phi_transpose():
+    p = datagen.star_pair(39, 18, 20, w=2, dk=2, db=1, noise=10.0, dtype=np.float64)
+    phi = brute.design_matrix(p.r, 2, 2, 2, 1, 1)
+    img = np.random.default_rng(4).normal(size=p.r.shape)
+    ref = phi.T @ img.ravel()
+    for u in [0, 5, 24, 25, 40, phi.shape[1] - 3, phi.shape[1] - 1]:
+        assert abs(oracle.phi_dot(p.r, img, 2, 2, 2, 1, 1, u) - ref[u]) < 1e-10 * np.abs(ref).max()
