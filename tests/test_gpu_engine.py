@@ -1,0 +1,91 @@
+"""Serving engine: continuous batching of independent pairs of uneven sizes.
+
+Each result must be the same alone and in the mix (bit for bit: every
+reduction has a fixed order and requests share no buffers), admission must
+refuse a request that can never fit the HBM budget, and requests that fit
+only one at a time must queue and complete.
+"""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+
+pytestmark = pytest.mark.gpu
+
+MIX = [
+    # n0, n1, w, dk, db
+    (64, 64, 2, 1, 1),
+    (96, 128, 3, 2, 2),
+    (256, 256, 5, 2, 2),
+    (48, 96, 2, 0, 0),
+    (192, 144, 4, 1, 2),
+]
+
+
+def _inputs(k, n0, n1, w, dk, db):
+    p = datagen.star_pair(300 + k, n0, n1, w=w, dk=dk, db=db, density=0.01, dtype=np.float32)
+    return torch.from_numpy(p.r).cuda(), torch.from_numpy(p.s).cuda()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_alone_equals_in_the_mix(sfft, prec):
+    pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
+    alone = []
+    with sfft.Context(0) as ctx:
+        for k, (n0, n1, w, dk, db) in enumerate(MIX):
+            p = sfft.Params(n0, n1, w, w, dk, db, 0, pr, sfft.F32)
+            R, S = _inputs(k, n0, n1, w, dk, db)
+            coef, d = ctx.run(p, R, S)
+            ctx.sync()
+            alone.append((p, R, S, coef.clone(), d.clone()))
+    with sfft.Context(0) as ctx:
+        ctx.engine_config(3)
+        jobs = []
+        for rep in range(3):
+            for k, (p, R, S, _, _) in enumerate(alone):
+                c = torch.full((p.num_unknowns,), float("nan"), dtype=torch.float64, device="cuda")
+                d = torch.full((p.n0, p.n1), float("nan"), dtype=torch.float32, device="cuda")
+                jobs.append((k, ctx.submit(p, R, S, R, S, c, d), c, d))
+        for k, t, c, d in jobs:
+            assert ctx.wait(t) == sfft.OK
+        torch.cuda.synchronize()
+        for k, t, c, d in jobs:
+            assert torch.equal(c, alone[k][3]), (prec, k)
+            assert torch.equal(d, alone[k][4]), (prec, k)
+        for k, t, c, d in jobs:
+            with pytest.raises(sfft.SfftError):
+                ctx.poll(t)   # a finished ticket is reported once
+
+
+def test_admission_refuses_what_can_never_fit(sfft):
+    small = sfft.Params(64, 64, 2, 2, 1, 1, 0, sfft.MIXED, sfft.F32)
+    big = sfft.Params(256, 256, 5, 5, 2, 2, 0, sfft.MIXED, sfft.F32)
+    budget = sfft.Context.workspace_bytes(small) + 4096
+    assert sfft.Context.workspace_bytes(big) > budget
+    with sfft.Context(0, hbm_budget_bytes=budget) as ctx:
+        R, S = _inputs(1, 256, 256, 5, 2, 2)
+        c = torch.empty(big.num_unknowns, dtype=torch.float64, device="cuda")
+        d = torch.empty((256, 256), dtype=torch.float32, device="cuda")
+        with pytest.raises(sfft.SfftError) as ei:
+            ctx.submit(big, R, S, R, S, c, d)
+        assert ei.value.code == sfft.E_NOMEM
+
+
+def test_requests_queue_until_memory_frees(sfft):
+    p = sfft.Params(128, 128, 3, 3, 2, 2, 0, sfft.MIXED, sfft.F32)
+    budget = int(sfft.Context.workspace_bytes(p) * 1.5)   # one workspace at a time
+    R, S = _inputs(2, 128, 128, 3, 2, 2)
+    with sfft.Context(0) as ref_ctx:
+        cref, dref = ref_ctx.run(p, R, S)
+        ref_ctx.sync()
+    with sfft.Context(0, hbm_budget_bytes=budget) as ctx:
+        ctx.engine_config(4)
+        outs = []
+        for _ in range(5):
+            c = torch.empty(p.num_unknowns, dtype=torch.float64, device="cuda")
+            d = torch.empty((128, 128), dtype=torch.float32, device="cuda")
+            outs.append((ctx.submit(p, R, S, R, S, c, d), c, d))
+        for t, c, d in outs:
+            assert ctx.wait(t) == sfft.OK
+            assert torch.equal(c, cref) and torch.equal(d, dref)
