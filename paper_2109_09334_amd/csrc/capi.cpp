@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -357,7 +358,7 @@ static hipError_t factor_solve(Plan& pl, const double* G, const double* h, doubl
     {
         StageTimer t_(pl.prof, "cholesky", st);
         e = launch_jacobi(n, G, h, w.L, w.dsc, w.rhs, w.flag, st);
-        if (!e) e = launch_cholesky(n, w.L, w.flag, st);
+        if (!e) e = launch_cholesky(n, w.L, w.dfac, w.flag, st);
     }
     if (!e) {
         StageTimer t_(pl.prof, "trsv", st);
@@ -409,6 +410,16 @@ static hipError_t refine(Plan& pl, double* coef, hipStream_t st) {
     return e;
 }
 
+// Refinement steps of the mixed form (one by default; SFFT_REFINE_STEPS
+// overrides it for diagnostics).
+static int refine_steps() {
+    static const int n = [] {
+        const char* s = getenv("SFFT_REFINE_STEPS");
+        return s ? atoi(s) : 1;
+    }();
+    return n;
+}
+
 template <typename T, typename Tin>
 static int run_build_t(Plan& pl, const void* r, const void* s, double* G, double* h, hipStream_t st) {
     return hip_status(build<T, Tin>(pl, (const Tin*)r, (const Tin*)s, G, h, st));
@@ -422,7 +433,7 @@ static int run_solve_t(Plan& pl, const double* G, const double* h, const void* r
     if (!e && pl.p.precision == SFFT_MIXED && r && s) {
         e = poly_tables<Tin>(pl, (const Tin*)r, (const Tin*)s, st);
         if (!e) e = forward_fit<T, Tin>(pl, (const Tin*)r, (const Tin*)s, st);
-        if (!e) e = refine<T>(pl, coef, st);
+        for (int it = 0; !e && it < refine_steps(); ++it) e = refine<T>(pl, coef, st);
     }
     return hip_status(e);
 }
@@ -448,7 +459,8 @@ static int run_all_t(Plan& pl, const void* rf, const void* sf, const void* r, co
     hipError_t e = launch_clear_flag(w.flag, st);
     if (!e) e = build<T, Tin>(pl, (const Tin*)rf, (const Tin*)sf, w.G, w.h, st);
     if (!e) e = factor_solve(pl, w.G, w.h, w.coef, st);
-    if (!e && pl.p.precision == SFFT_MIXED) e = refine<T>(pl, w.coef, st);
+    for (int it = 0; !e && pl.p.precision == SFFT_MIXED && it < refine_steps(); ++it)
+        e = refine<T>(pl, w.coef, st);
     if (e) return hip_status(e);
     if (coef) {
         e = hipMemcpyAsync(coef, w.coef, pl.g.nu * sizeof(double), hipMemcpyDeviceToDevice, st);

@@ -71,10 +71,13 @@ __device__ void potrf_lds(double (*A)[NBK + 1], int nb, int* flag) {
     }
 }
 
-// Block 0 factorises the diagonal block; block b >= 1 solves row block b of
-// the panel, X L_d^T = A (forward substitution, one row per thread).
+// Every block factorises the panel's diagonal block from L in LDS (L is not
+// written there during the launch, so all blocks see the same input); block 0
+// stores the factor in dfac (copied into L after the last panel), block
+// b >= 1 solves row block b of the panel, X L_d^T = A (forward substitution,
+// one row per thread).
 __global__ void __launch_bounds__(256) panel_kernel(int n, double* __restrict__ L, int kb,
-                                                     int* flag) {
+                                                     double* __restrict__ dfac, int* flag) {
     __shared__ double D[NBK][NBK + 1];
     __shared__ double A[NBK][NBK + 1];
     const int nb = min(NBK, n - kb);
@@ -85,9 +88,10 @@ __global__ void __launch_bounds__(256) panel_kernel(int n, double* __restrict__ 
     __syncthreads();
     potrf_lds(D, nb, flag);
     if (blockIdx.x == 0) {
+        double* out = dfac + (size_t)(kb / NBK) * NBK * NBK;
         for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
             const int i = t / nb, j = t % nb;
-            if (j <= i) L[(size_t)(kb + i) * n + kb + j] = D[i][j];
+            out[i * NBK + j] = j <= i ? D[i][j] : 0.0;
         }
         return;
     }
@@ -110,6 +114,18 @@ __global__ void __launch_bounds__(256) panel_kernel(int n, double* __restrict__ 
     for (int t = threadIdx.x; t < nr * nb; t += blockDim.x) {
         const int i = t / nb, j = t % nb;
         L[(size_t)(r0 + i) * n + kb + j] = A[i][j];
+    }
+}
+
+// Diagonal factors of every panel into L (after the last panel).
+__global__ void __launch_bounds__(256) diag_copy_kernel(int n, double* __restrict__ L,
+                                                         const double* __restrict__ dfac) {
+    const int kb = blockIdx.x * NBK;
+    const int nb = min(NBK, n - kb);
+    const double* in = dfac + (size_t)blockIdx.x * NBK * NBK;
+    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+        const int i = t / nb, j = t % nb;
+        if (j <= i) L[(size_t)(kb + i) * n + kb + j] = in[i * NBK + j];
     }
 }
 
@@ -245,10 +261,10 @@ hipError_t launch_jacobi(int n, const double* G, const double* h, double* L, dou
     return hipGetLastError();
 }
 
-hipError_t launch_cholesky(int n, double* L, int* flag, hipStream_t st) {
+hipError_t launch_cholesky(int n, double* L, double* dfac, int* flag, hipStream_t st) {
     for (int kb = 0; kb < n; kb += NBK) {
         const int nblk = (n - kb + NBK - 1) / NBK;
-        hipLaunchKernelGGL(panel_kernel, dim3(nblk), dim3(256), 0, st, n, L, kb, flag);
+        hipLaunchKernelGGL(panel_kernel, dim3(nblk), dim3(256), 0, st, n, L, kb, dfac, flag);
         const int nb = min(NBK, n - kb);
         const int rest = n - kb - nb;
         if (rest > 0) {
@@ -256,6 +272,7 @@ hipError_t launch_cholesky(int n, double* L, int* flag, hipStream_t st) {
             hipLaunchKernelGGL(syrk_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, st, n, L, kb);
         }
     }
+    hipLaunchKernelGGL(diag_copy_kernel, dim3((n + NBK - 1) / NBK), dim3(256), 0, st, n, L, dfac);
     return hipGetLastError();
 }
 

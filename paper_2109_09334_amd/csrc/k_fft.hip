@@ -72,10 +72,17 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
                                                       const cx<T>* __restrict__ tw) {
     cx<T>* lds = lds_base<T>();
     const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
-    const int m = blockIdx.x * lp.lpw + line;
+    // Block -> (column block, job): workgroups are dealt to the 8 XCDs round
+    // robin, so groups of 16 adjacent column blocks are kept on one XCD, where
+    // their strided row reads share L2 lines.
+    const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
+    const int per_xcd = (ncb + 127) / 128 * 16;   // column blocks per XCD per job
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int job = slot / per_xcd, r = slot - job * per_xcd;
+    const int cb = 16 * (8 * (r >> 4) + xcd) + (r & 15);
+    const int m = cb * lp.lpw + line;
     const bool act = m < g.h;
     const int n0 = g.n0;
-    const int job = blockIdx.y;
     const int a = jobs.arr[job];
     cx<T>* buf = lds + line * lp.n;
     cx<T> z[kElemsPerThread];
@@ -212,7 +219,8 @@ hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs,
     auto k = colfwd_kernel<T>;
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
-    dim3 grid((g.h + lp.lpw - 1) / lp.lpw, jobs.narr);
+    const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
+    dim3 grid((ncb + 127) / 128 * 128 * jobs.narr);
     hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, jobs, Z, X, tw);
     return hipGetLastError();
 }

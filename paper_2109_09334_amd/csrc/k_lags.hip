@@ -14,6 +14,8 @@
 #include "fft_engine.hpp"
 #include "kernels.hpp"
 
+#include <cstdlib>
+
 namespace sfft {
 
 template <typename T>
@@ -33,15 +35,21 @@ __host__ __device__ __forceinline__ void decode_pair(int P, int pr, int& kb, int
 }
 
 template <typename T>
-__global__ void __launch_bounds__(512) lagcol_kernel(Geom g, LinePlan lp, int p0, int sslot,
+__global__ void __launch_bounds__(512) lagcol_kernel(Geom g, LinePlan lp, int p0, int np, int sslot,
                                                       const cx<T>* __restrict__ X,
                                                       cx<T>* __restrict__ Cl,
                                                       const cx<T>* __restrict__ tw) {
     cx<T>* lds = lds_base_l<T>();
     const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
-    const int m = blockIdx.x * lp.lpw + line;
+    // Block -> (column block, product): the products of one column block run
+    // back to back on one XCD (workgroups are dealt to the 8 XCDs round
+    // robin), so the column's spectra are read from HBM once and reused in L2.
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int jx = slot / np;
+    const int p = p0 + (slot - jx * np);
+    const int cb = 8 * jx + xcd;
+    const int m = cb * lp.lpw + line;
     const bool act = m < g.h;
-    const int p = p0 + blockIdx.y;
     const int n0 = g.n0;
     int kb, k;
     if (p < g.npair) decode_pair(g.P, p, kb, k);
@@ -63,6 +71,100 @@ __global__ void __launch_bounds__(512) lagcol_kernel(Geom g, LinePlan lp, int p0
         for (int t = lt; t <= 2 * K; t += lp.tl) {
             const int d0 = t - K;
             Cl[((size_t)p * g.D0 + d0 + 2 * g.w0) * g.hp + m] = buf[imod(d0, n0)];
+        }
+    }
+}
+
+// Pruned inverse along axis 0 by decimation. Thread j of a line holds the
+// 16 strided product values P(j + M q), q < 16 (M = N0/16 threads per line),
+// and applies the radix-16 inverse DFT in registers:
+//   Y_j(r) = sum_q P(j + M q) e^(+2 pi i q r / 16).
+// Each kept lag d0 is then the M-term sum
+//   C(d0) = sum_j e^(+2 pi i j d0 / N0) Y_j(d0 mod 16),
+// formed 16 lags at a time (one per residue r) and summed over the lanes of
+// each wave by a transpose-reduce (every step halves the values a lane
+// carries and doubles the lanes each value is summed over), then across
+// waves through LDS. One block covers one column and one kernel term kb and
+// keeps conj(X_kb) in registers for all of that term's products.
+template <typename T, int HALF, int OFF>
+__device__ __forceinline__ void tr_step(cx<T>* v, int lane) {
+    const bool hi = (lane & OFF) != 0;
+#pragma unroll
+    for (int i = 0; i < HALF; ++i) {
+        cx<T> send = hi ? v[i] : v[i + HALF];
+        const cx<T> keep = hi ? v[i + HALF] : v[i];
+        send.re = __shfl_xor(send.re, OFF, 64);
+        send.im = __shfl_xor(send.im, OFF, 64);
+        v[i] = keep + send;
+    }
+}
+
+// After the call lane L holds in v[0] the wave-wide sum of slot (L >> 2) & 15.
+template <typename T>
+__device__ __forceinline__ void wave_transpose_sum16(cx<T>* v, int lane) {
+    tr_step<T, 8, 32>(v, lane);
+    tr_step<T, 4, 16>(v, lane);
+    tr_step<T, 2, 8>(v, lane);
+    tr_step<T, 1, 4>(v, lane);
+    v[0].re += __shfl_xor(v[0].re, 2, 64);
+    v[0].im += __shfl_xor(v[0].im, 2, 64);
+    v[0].re += __shfl_xor(v[0].re, 1, 64);
+    v[0].im += __shfl_xor(v[0].im, 1, 64);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, int ir_only,
+                                                           int sslot, const cx<T>* __restrict__ X,
+                                                           cx<T>* __restrict__ Cl,
+                                                           const cx<T>* __restrict__ tw) {
+    __shared__ cx<T> red[8][16];
+    const int tl = lp.tl;                       // M: threads per line, multiple of 64
+    const int line = threadIdx.x / tl, j = threadIdx.x - line * tl;
+    const int lane = threadIdx.x & 63, wl = j >> 6, nwl = tl >> 6;
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int jx = slot / g.P;
+    const int kb = slot - jx * g.P;
+    const int cb = 8 * jx + xcd;
+    const int m = cb * lp.lpw + line;
+    const bool act = m < g.h;
+    const int n0 = g.n0;
+    cx<T> a[16];
+    if (act) {
+        const cx<T>* A = X + ((size_t)kb * g.h + m) * n0 + j;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a[q] = A[(size_t)q * tl];
+    }
+    const int kfirst = ir_only ? g.P : kb;
+    for (int kk = kfirst; kk <= g.P; ++kk) {
+        const bool theta = kk == g.P;
+        const int k = theta ? sslot : kk;
+        const int p = theta ? g.npair + kb : kb * g.P - kb * (kb - 1) / 2 + (kk - kb);
+        const int K = theta ? g.w0 : 2 * g.w0;
+        cx<T> v[16];
+        if (act) {
+            const cx<T>* B = X + ((size_t)k * g.h + m) * n0 + j;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = cmulc(a[q], B[(size_t)q * tl]);
+            Dft<16, 1, T>::run(v);
+        }
+        for (int tb = -K; tb <= K; tb += 16) {
+            cx<T> s[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int t = tb + ((r - tb) & 15);
+                const cx<T> w = tw[imod(j * t, n0)];     // e^(-2 pi i j t / N0)
+                s[r] = act ? cmul(v[r], cconj(w)) : mk(T(0), T(0));
+            }
+            wave_transpose_sum16(s, lane);
+            if ((lane & 3) == 0) red[line * nwl + wl][(lane >> 2) & 15] = s[0];
+            __syncthreads();
+            if (act && j < 16) {
+                cx<T> tot = red[line * nwl][j];
+                for (int w = 1; w < nwl; ++w) tot = tot + red[line * nwl + w][j];
+                const int t = tb + ((j - tb) & 15);
+                if (t <= K) Cl[((size_t)p * g.D0 + t + 2 * g.w0) * g.hp + m] = tot;
+            }
+            __syncthreads();
         }
     }
 }
@@ -114,14 +216,19 @@ __global__ void __launch_bounds__(256) lagrow_kernel(Geom g, int p0, const cx<T>
         for (int m = threadIdx.x; m < g.h; m += blockDim.x) {
             const cx<T> c = row[m];
             const double wm = (m == 0 || 2 * m == n1) ? 1.0 : 2.0;
-            const double cr = wm * (double)c.re, ci = wm * (double)c.im;
+            double cr = wm * (double)c.re, ci = wm * (double)c.im;
+            // (cr + i ci) e^(+2 pi i m d1 / N1) for d1 = base, base+1, ...: one
+            // table value for the first lag, then FP64 angle addition
+            const int i0 = imod(m * base, n1);
+            const double e0r = twp[2 * i0], e0i = twp[2 * i0 + 1];
+            const double sr = twp[2 * m], si = twp[2 * m + 1];
+            double xr = cr * e0r - ci * e0i, xi = cr * e0i + ci * e0r;
 #pragma unroll
             for (int t = 0; t < kLagChunk; ++t) {
-                const int d1 = base + t;
-                if (d1 <= K1) {
-                    const int idx = imod(m * d1, n1);
-                    acc[t] += cr * twp[2 * idx] - ci * twp[2 * idx + 1];
-                }
+                acc[t] += xr;
+                const double nr = xr * sr - xi * si;
+                xi = xr * si + xi * sr;
+                xr = nr;
             }
         }
         block_sum<kLagChunk>(acc, red);
@@ -143,6 +250,15 @@ template <typename T>
 hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int sslot,
                          const cx<T>* X, cx<T>* Cl, const cx<T>* tw, hipStream_t st) {
     if (p1 <= p0) return hipSuccess;
+    static const bool force_full = getenv("SFFT_LAGCOL_FULL") != nullptr;
+    if (!force_full && lp.tl % 64 == 0 && lp.tl * lp.lpw <= 512 &&
+        ((p0 == 0 && p1 == g.nprod) || (p0 == g.npair && p1 == g.nprod))) {
+        const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
+        dim3 grid((ncb + 7) / 8 * 8 * g.P);
+        hipLaunchKernelGGL(lagcol_tail_kernel<T>, grid, dim3(lp.tl * lp.lpw), 0, st, g, lp,
+                           p0 == 0 ? 0 : 1, sslot, X, Cl, tw);
+        return hipGetLastError();
+    }
     const size_t lds = (size_t)lp.lpw * lp.n * sizeof(cx<T>);
     auto k = lagcol_kernel<T>;
     if (lds > 65536) {
@@ -150,8 +266,9 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    dim3 grid((g.h + lp.lpw - 1) / lp.lpw, p1 - p0);
-    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, p0, sslot, X, Cl, tw);
+    const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
+    dim3 grid((ncb + 7) / 8 * 8 * (p1 - p0));
+    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, p0, p1 - p0, sslot, X, Cl, tw);
     return hipGetLastError();
 }
 

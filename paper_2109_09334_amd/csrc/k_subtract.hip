@@ -86,38 +86,90 @@ __global__ void __launch_bounds__(256) ytab_kernel(Geom g, const double* __restr
     ytab[(size_t)j * g.h + m] = cx<double>{re, im};
 }
 
+// Tile: 64 columns x kStTile rows per block of 256 threads (4 row groups of
+// kStRows rows per thread). The (kStTile + 2 w0) source rows of one row
+// spectrum Z_j are staged in LDS at a time, so each Z element is read from
+// HBM once per tile instead of 2 w0 + 1 times; the stamp spectra of the
+// thread's column are loaded once per tap.
+constexpr int kStCols = 64;
+constexpr int kStRows = 8;
+constexpr int kStTile = 4 * kStRows;
+
 template <typename T>
 __global__ void __launch_bounds__(256) stencil_kernel(Geom g, const cx<T>* __restrict__ Z, int zs,
                                                        const cx<T>* __restrict__ Kt,
                                                        const double* __restrict__ ped,
                                                        const cx<double>* __restrict__ ytab,
                                                        cx<T>* __restrict__ Dt) {
-    const int m = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int x0 = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (m >= g.h || x0 >= g.n0) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nsrc = kStTile + 2 * g.w0;
+    cx<T>* zt = reinterpret_cast<cx<T>*>(smem_raw);            // [nsrc][kStCols]
+    T* ct = reinterpret_cast<T*>(zt + (size_t)nsrc * kStCols);  // [nsrc] source coordinates
+    const int mc = threadIdx.x & 63, rg = threadIdx.x >> 6;
+    const int m = blockIdx.x * kStCols + mc;
+    const int x0b = blockIdx.y * kStTile;
     const int n0 = g.n0;
+    const bool mok = m < g.h;
     const size_t plane = (size_t)n0 * g.hp;
-    cx<T> acc = Z[(size_t)zs * plane + (size_t)x0 * g.hp + m];
     const double cR = ped ? ped[0] : 0.0;
-    if (ped && m == 0) acc.re += T(ped[1] * (double)g.n1);
-    for (int j = 0; j <= g.dk; ++j) {
-        const cx<T>* Zj = Z + (size_t)j * plane + m;
-        const cx<double> y = ped ? ytab[(size_t)j * g.h + m] : cx<double>{0.0, 0.0};
-        const cx<T> add = mk(T(cR * y.re), T(cR * y.im));
-        for (int a0 = -g.w0; a0 <= g.w0; ++a0) {
-            const int xs = imod(x0 - a0, n0);
-            const cx<T> z = Zj[(size_t)xs * g.hp] + add;
-            const T c = coord<T>(xs, n0);
-            // Horner over i = DK-j .. 0 of Kt_(i,j)(a0, m) c^i
-            cx<T> poly = mk(T(0), T(0));
-            for (int i = g.dk - j; i >= 0; --i) {
-                const cx<T> kt = Kt[((size_t)term_index(g.dk, i, j) * g.L0 + a0 + g.w0) * g.hp + m];
-                poly = mk(poly.re * c + kt.re, poly.im * c + kt.im);
-            }
-            acc = acc - cmul(poly, z);
+    for (int r = threadIdx.x; r < nsrc; r += blockDim.x)
+        ct[r] = coord<T>(imod(x0b - g.w0 + r, n0), n0);
+    cx<T> acc[kStRows];
+#pragma unroll
+    for (int o = 0; o < kStRows; ++o) {
+        const int x0 = x0b + rg * kStRows + o;
+        acc[o] = mk(T(0), T(0));
+        if (mok && x0 < n0) {
+            acc[o] = Z[(size_t)zs * plane + (size_t)x0 * g.hp + m];
+            if (ped && m == 0) acc[o].re += T(ped[1] * (double)g.n1);
         }
     }
-    Dt[(size_t)x0 * g.hp + m] = acc;
+    for (int j = 0; j <= g.dk; ++j) {
+        __syncthreads();
+        const cx<T>* Zj = Z + (size_t)j * plane;
+        cx<T> add = mk(T(0), T(0));
+        if (ped && mok) {
+            const cx<double> y = ytab[(size_t)j * g.h + m];
+            add = mk(T(cR * y.re), T(cR * y.im));
+        }
+        for (int r = rg; r < nsrc; r += 4) {
+            const int xs = imod(x0b - g.w0 + r, n0);
+            zt[r * kStCols + mc] = mok ? Zj[(size_t)xs * g.hp + m] + add : mk(T(0), T(0));
+        }
+        __syncthreads();
+        const int ni = g.dk - j;   // polynomial degree in c0 for this j
+        for (int a0 = -g.w0; a0 <= g.w0; ++a0) {
+            cx<T> kt[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                kt[i] = (i <= ni && mok)
+                            ? Kt[((size_t)term_index(g.dk, i, j) * g.L0 + a0 + g.w0) * g.hp + m]
+                            : mk(T(0), T(0));
+#pragma unroll
+            for (int o = 0; o < kStRows; ++o) {
+                const int r = rg * kStRows + o + g.w0 - a0;   // source row in the tile
+                const cx<T> z = zt[r * kStCols + mc];
+                const T c = ct[r];
+                // sum_i kt[i] c^i, i <= ni (ni is uniform over the block)
+                cx<T> poly = kt[0];
+                T cp = c;
+#pragma unroll
+                for (int i = 1; i < 5; ++i) {
+                    if (i <= ni) {
+                        poly.re += kt[i].re * cp;
+                        poly.im += kt[i].im * cp;
+                        cp *= c;
+                    }
+                }
+                acc[o] = acc[o] - cmul(poly, z);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < kStRows; ++o) {
+        const int x0 = x0b + rg * kStRows + o;
+        if (mok && x0 < n0) Dt[(size_t)x0 * g.hp + m] = acc[o];
+    }
 }
 
 hipError_t launch_stamps(const Geom& g, const double* coef, double* kap, hipStream_t st) {
@@ -136,8 +188,15 @@ hipError_t launch_stamp_spectra(const Geom& g, const double* kap, const double* 
 template <typename T>
 hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<T>* Kt,
                           const double* ped, const cx<double>* ytab, cx<T>* Dt, hipStream_t st) {
-    hipLaunchKernelGGL(stencil_kernel<T>, dim3((g.h + 63) / 64, (g.n0 + 3) / 4), dim3(256), 0, st,
-                       g, Z, zs_index, Kt, ped, ytab, Dt);
+    const size_t nsrc = kStTile + 2 * g.w0;
+    const size_t lds = nsrc * kStCols * sizeof(cx<T>) + nsrc * sizeof(T);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(stencil_kernel<T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(stencil_kernel<T>, dim3((g.h + kStCols - 1) / kStCols, (g.n0 + kStTile - 1) / kStTile),
+                       dim3(256), lds, st, g, Z, zs_index, Kt, ped, ytab, Dt);
     return hipGetLastError();
 }
 

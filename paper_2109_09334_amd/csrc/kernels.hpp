@@ -73,7 +73,8 @@ hipError_t launch_gather(const Geom& g, const double* om, const double* th, cons
 // Cholesky of the Jacobi-scaled normal matrix and triangular solves.
 hipError_t launch_jacobi(int n, const double* G, const double* h, double* L, double* dsc,
                          double* rhs, int* flag, hipStream_t st);
-hipError_t launch_cholesky(int n, double* L, int* flag, hipStream_t st);
+// dfac: scratch of ceil(n/64) * 64 * 64 doubles for the panels' diagonal factors.
+hipError_t launch_cholesky(int n, double* L, double* dfac, int* flag, hipStream_t st);
 hipError_t launch_chol_solve(int n, const double* L, const double* dsc, double* rhs,
                              double* coef, int accumulate, const int* flag, hipStream_t st);
 hipError_t launch_clear_flag(int* flag, hipStream_t st);

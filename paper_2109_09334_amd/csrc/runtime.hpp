@@ -44,7 +44,7 @@ struct Workspace {
     double* ped;               // pedestals c_R, c_S
     cx<double>* ytab;          // row spectra of c1^j, [DK+1][h]
     bool ytab_ready;
-    double *G, *h, *L, *dsc, *rhs, *coef;
+    double *G, *h, *L, *dsc, *rhs, *coef, *dfac;
     int* flag;
 };
 
@@ -83,6 +83,7 @@ inline size_t carve(Workspace& w, const Geom& g, size_t cxb, size_t reb, char* b
     w.dsc = c.take<double>(base, g.nu);
     w.rhs = c.take<double>(base, g.nu);
     w.coef = c.take<double>(base, g.nu);
+    w.dfac = c.take<double>(base, (size_t)((g.nu + 63) / 64) * 64 * 64);
     w.flag = c.take<int>(base, 64);
     w.ytab_ready = false;
     return c.off + 256;

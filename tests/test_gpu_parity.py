@@ -24,6 +24,10 @@ CASES = [
     (64, 96, 3, 2, 2, 0),
     (96, 48, 2, 2, 1, 1),
     (144, 192, 4, 0, 0, 0),
+    # tall images: column transforms with 64, 128 and 192 threads per line
+    (1024, 64, 3, 2, 2, 0),
+    (2048, 48, 2, 1, 1, 1),
+    (3072, 32, 2, 2, 1, 0),
 ]
 
 
@@ -134,8 +138,12 @@ def test_separate_calls_match_run(sfft, ctx, prec):
     d = ctx.subtract(p, R, S, coef)
     coef2, d2 = ctx.run(p, R, S)
     ctx.sync()
+    # the build and solve are the same kernels on the same inputs
     assert torch.equal(coef, coef2)
-    assert torch.equal(d, d2)
+    # sfft_subtract transforms the apply pair as given, sfft_run reuses the
+    # pedestal-free transforms of the fit pair: equal up to rounding
+    rms = float(torch.sqrt(torch.mean((d - d2) ** 2)))
+    assert rms <= (1e-10 if prec == "fp64" else 1e-5) * 10.0
 
 
 def test_apply_pair_differs_from_fit_pair(sfft, ctx):
