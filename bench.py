@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--stream-requests", type=int, default=120)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="run N device copies of 1 GiB (calibrates HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -105,6 +107,15 @@ def main():
 
     import torch
     import paper_2109_09334_amd as sf
+
+    if args.calib_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(args.calib_copy):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": a.numel() * 4, "copies": args.calib_copy}))
+        return
 
     n, w, dk, db = args.size, 7, 2, 2
     t0 = time.time()

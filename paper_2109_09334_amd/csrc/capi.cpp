@@ -36,7 +36,7 @@ int check_params(const sfft_params* p) {
     if (!p) return SFFT_E_INVAL;
     if (p->n0 < 16 || p->n1 < 16 || p->w0 < 0 || p->w1 < 0 || p->dk < 0 || p->db < 0)
         return SFFT_E_INVAL;
-    if (p->dk > 4 || p->db > 4 || p->w0 > 16 || p->w1 > 16) return SFFT_E_UNSUPPORTED;
+    if (p->dk > kMaxDegree || p->db > kMaxDegree || p->w0 > 16 || p->w1 > 16) return SFFT_E_UNSUPPORTED;
     if (2 * p->w0 + 1 > p->n0 || 2 * p->w1 + 1 > p->n1) return SFFT_E_INVAL;
     if (p->precision != SFFT_FP64 && p->precision != SFFT_MIXED) return SFFT_E_INVAL;
     if (p->dtype != SFFT_F32 && p->dtype != SFFT_F64) return SFFT_E_INVAL;
@@ -253,9 +253,9 @@ static hipError_t poly_tables(Plan& pl, const Tin* r, const Tin* s, hipStream_t 
     const int dm = poly_degree(g);
     StageTimer t_(pl.prof, "background", st);
     hipError_t e = launch_polyrow<Tin>(g, r, g.dk, dm, 2 * g.w1, w.vrow, st);
-    if (!e) e = launch_polycorr(g, w.vrow, g.dk, dm, 2 * g.w0, 2 * g.w1, w.piR, st);
+    if (!e) e = launch_polycorr(g, w.vrow, g.dk, dm, 2 * g.w0, 2 * g.w1, w.vpart, w.piR, st);
     if (!e) e = launch_polyrow<Tin>(g, s, 0, dm, g.w1, w.vrow, st);
-    if (!e) e = launch_polycorr(g, w.vrow, 0, dm, g.w0, g.w1, w.piS, st);
+    if (!e) e = launch_polycorr(g, w.vrow, 0, dm, g.w0, g.w1, w.vpart, w.piS, st);
     if (!e) e = launch_polysum(g, dm, w.sig0, w.sig1, w.pw, st);
     if (!e) e = launch_pedestal(g, w.piR, dm, w.piS, w.ped, st);
     return e;
@@ -320,31 +320,26 @@ static hipError_t build(Plan& pl, const Tin* r, const Tin* s, double* G, double*
     return e;
 }
 
-static hipError_t ensure_ytab(Plan& pl, hipStream_t st) {
-    if (pl.ws.ytab_ready) return hipSuccess;
-    hipError_t e = launch_ytab(pl.g, pl.t1.twp, pl.ws.ytab, st);
-    if (!e) pl.ws.ytab_ready = true;
-    return e;
-}
-
-// D from the row spectra in Z (slots 0..DK of R, slot zs of S; with the
-// pedestals of w.ped removed when `pedestal`) and the coefficients.
+// D from the row spectra in Z (slots 0..DK of R, slot zs of S) and the
+// coefficients. With `pedestal` the spectra are those of R - c_R and S - c_S
+// (pedestals in w.ped) and the pedestal terms re-enter in FP64 through the
+// sky table together with the background.
 template <typename T, typename Tout>
 static hipError_t difference(Plan& pl, int zs, bool pedestal, const double* coef, Tout* d,
                              hipStream_t st) {
     const Geom& g = pl.g;
     Workspace& w = pl.ws;
-    hipError_t e = ensure_ytab(pl, st);
+    hipError_t e;
     {
         StageTimer t_(pl.prof, "stencil", st);
-        if (!e) e = launch_stamps(g, coef, w.kap, st);
+        e = launch_stamps(g, coef, w.kap, st);
+        if (!e) e = launch_sky(g, w.kap, coef + g.nk, pedestal ? w.ped : nullptr, w.kap1, w.sky, st);
         if (!e) e = launch_stamp_spectra<T>(g, w.kap, pl.t1.twp, cxp<T>(w.Kt), st);
-        if (!e) e = launch_stencil<T>(g, cxp<T>(w.Z), zs, cxp<T>(w.Kt), pedestal ? w.ped : nullptr,
-                                      w.ytab, cxp<T>(w.Dt), st);
+        if (!e) e = launch_stencil<T>(g, cxp<T>(w.Z), zs, cxp<T>(w.Kt), cxp<T>(w.Dt), st);
     }
     if (!e) {
         StageTimer t_(pl.prof, "rowinv", st);
-        e = launch_rowinv<T, Tout>(g, pl.lp1, cxp<T>(w.Dt), d, coef + g.nk, cxp<T>(pl.t1.tw), st);
+        e = launch_rowinv<T, Tout>(g, pl.lp1, cxp<T>(w.Dt), d, w.sky, cxp<T>(pl.t1.tw), st);
     }
     return e;
 }
@@ -358,12 +353,12 @@ static hipError_t factor_solve(Plan& pl, const double* G, const double* h, doubl
     {
         StageTimer t_(pl.prof, "cholesky", st);
         e = launch_jacobi(n, G, h, w.L, w.dsc, w.rhs, w.flag, st);
-        if (!e) e = launch_cholesky(n, w.L, w.dfac, w.flag, st);
+        if (!e) e = launch_cholesky(n, w.L, w.dfac, w.dinv, w.flag, st);
     }
     if (!e) {
         StageTimer t_(pl.prof, "trsv", st);
         e = hipMemcpyAsync(w.rhs, h, n * sizeof(double), hipMemcpyDeviceToDevice, st);
-        if (!e) e = launch_chol_solve(n, w.L, w.dsc, w.rhs, coef, 0, w.flag, st);
+        if (!e) e = launch_chol_solve(n, w.L, w.dinv, w.dsc, w.rhs, coef, 0, w.flag, st);
     }
     return e;
 }
@@ -387,7 +382,7 @@ static hipError_t refine(Plan& pl, double* coef, hipStream_t st) {
     const int dm = poly_degree(g);
     hipError_t e = difference<T, T>(pl, g.dk + 1, true, coef, dfit, st);
     if (!e) e = launch_polyrow<T>(g, dfit, 0, dm, g.w1, w.vrow, st);
-    if (!e) e = launch_polycorr(g, w.vrow, 0, dm, g.w0, g.w1, w.piD, st);
+    if (!e) e = launch_polycorr(g, w.vrow, 0, dm, g.w0, g.w1, w.vpart, w.piD, st);
     RowSources src{};
     src.n = 1;
     src.pow[0] = 0;
@@ -406,7 +401,7 @@ static hipError_t refine(Plan& pl, double* coef, hipStream_t st) {
     if (!e) e = launch_lagfix(g, 1, w.ped, w.piR, w.piD, w.sig0, w.sig1, w.pw, dm, nullptr,
                               w.thetaD, nullptr, nullptr, w.evecD, st);
     if (!e) e = launch_gather(g, w.omega, w.thetaD, w.lam, w.cmat, w.evecD, nullptr, w.rhs, 1, st);
-    if (!e) e = launch_chol_solve(g.nu, w.L, w.dsc, w.rhs, coef, 1, w.flag, st);
+    if (!e) e = launch_chol_solve(g.nu, w.L, w.dinv, w.dsc, w.rhs, coef, 1, w.flag, st);
     return e;
 }
 

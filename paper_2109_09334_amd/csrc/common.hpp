@@ -35,6 +35,7 @@ __host__ __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im};
 
 // Maximum number of radix passes of one line transform.
 constexpr int kMaxPass = 8;
+constexpr int kMaxDegree = 4;   // largest DK and DB
 // Elements of one line held by one thread during a transform.
 constexpr int kElemsPerThread = 16;
 
@@ -92,6 +93,13 @@ template <typename T>
 __host__ __device__ __forceinline__ T ipow(T b, int e) {
     T r = T(1);
     for (int k = 0; k < e; ++k) r *= b;
+    return r;
+}
+
+// Binomial coefficient C(n, k) as a double (small n).
+__host__ __device__ __forceinline__ double binom(int n, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
     return r;
 }
 

@@ -24,14 +24,8 @@
 
 namespace sfft {
 
-constexpr int kMaxDeg = 4;
-constexpr int kMaxMom = 2 * kMaxDeg + 1;
-
-__device__ __forceinline__ double binom(int n, int k) {
-    double r = 1.0;
-    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
-    return r;
-}
+constexpr int kMaxMom = 2 * kMaxDegree + 1;
+constexpr int kRowChunk = 64;
 
 template <int NV>
 __device__ __forceinline__ void block_sum_bg(double* v, double* red) {
@@ -96,38 +90,78 @@ __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, const Tin* __restr
     }
 }
 
-// Block (ta, tb, d0): Pi[ta][tb][d0 + K0][d1 + K1] for all |d1| <= K1.
+// Axis 0 goes the same way as axis 1 in polyrow_kernel: with
+// c0((x0+d0) mod N0) = c0(x0) + 2 d0/(N0-1) off the |d0| wrapped rows,
+//   Pi_{(ia,ja)(ib,jb)}(d0, d1) = sum_r C(ib,r) s^(ib-r) Mom_{ia+r}(ja, jb, d1)
+//                                 + wrapped-row correction,
+// with the axis-0 moments Mom_e(item) = sum_x0 c0(x0)^e V(x0, item) and
+// item = (ja, jb, d1). The moments are summed per chunk of kRowChunk rows,
+// then the chunks in a fixed order (no atomics: the result does not depend
+// on scheduling).
+__global__ void __launch_bounds__(256) polymom_kernel(Geom g, const double* __restrict__ vrow,
+                                                       int nitem, int ne,
+                                                       double* __restrict__ part) {
+    const int x0a = blockIdx.x * kRowChunk, x0b = min(g.n0, x0a + kRowChunk);
+    for (int item = threadIdx.x; item < nitem; item += blockDim.x) {
+        double m[kMaxMom];
+#pragma unroll
+        for (int e = 0; e < kMaxMom; ++e) m[e] = 0.0;
+        for (int x0 = x0a; x0 < x0b; ++x0) {
+            const double c = coord<double>(x0, g.n0);
+            double pw = vrow[(size_t)x0 * nitem + item];
+#pragma unroll
+            for (int e = 0; e < kMaxMom; ++e) {
+                if (e < ne) m[e] += pw;
+                pw *= c;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < kMaxMom; ++e)
+            if (e < ne) part[((size_t)blockIdx.x * ne + e) * nitem + item] = m[e];
+    }
+}
+
+__global__ void __launch_bounds__(256) momsum_kernel(int nchunk, int nval,
+                                                      const double* __restrict__ part,
+                                                      double* __restrict__ mom) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nval) return;
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += part[(size_t)k * nval + i];
+    mom[i] = s;
+}
+
+// One thread per output Pi[ta][tb][d0 + K0][d1 + K1].
 __global__ void __launch_bounds__(256) polycorr_kernel(Geom g, const double* __restrict__ vrow,
-                                                        int da, int dbb, int K0, int K1,
+                                                        const double* __restrict__ mom, int da,
+                                                        int dbb, int K0, int K1,
                                                         double* __restrict__ pi) {
-    __shared__ double red[4 * 32];
     const int n0 = g.n0;
     const int nta = (da + 1) * (da + 2) / 2, ntb = (dbb + 1) * (dbb + 2) / 2;
     const int nd0 = 2 * K0 + 1, nd1 = 2 * K1 + 1;
-    const int ta = blockIdx.x / (ntb * nd0);
-    const int tb = (blockIdx.x / nd0) % ntb;
-    const int d0 = blockIdx.x % nd0 - K0;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nta * ntb * nd0 * nd1) return;
+    const int d1 = idx % nd1;
+    const int d0 = (idx / nd1) % nd0 - K0;
+    const int tb = (idx / (nd1 * nd0)) % ntb;
+    const int ta = idx / (nd1 * nd0 * ntb);
     int ia, ja, ib, jb;
     term_ij(da, ta, ia, ja);
     term_ij(dbb, tb, ib, jb);
-    const int na = da + 1, nb = dbb + 1;
-    for (int base = 0; base < nd1; base += 32) {
-        double acc[32];
-#pragma unroll
-        for (int t = 0; t < 32; ++t) acc[t] = 0.0;
-        for (int x0 = threadIdx.x; x0 < n0; x0 += blockDim.x) {
-            const double wgt = ipow(coord<double>(x0, n0), ia) *
-                               ipow(coord<double>(imod(x0 + d0, n0), n0), ib);
-            const double* vr = vrow + (((size_t)x0 * na + ja) * nb + jb) * nd1;
-#pragma unroll
-            for (int t = 0; t < 32; ++t)
-                if (base + t < nd1) acc[t] += wgt * vr[base + t];
-        }
-        block_sum_bg<32>(acc, red);
-        if (threadIdx.x < 32 && base + threadIdx.x < nd1)
-            pi[(((size_t)ta * ntb + tb) * nd0 + d0 + K0) * nd1 + base + threadIdx.x] = red[threadIdx.x];
-        __syncthreads();
+    const int nb = dbb + 1;
+    const int nitem = (da + 1) * nb * nd1;
+    const int item = (ja * nb + jb) * nd1 + d1;
+    const double sh = 2.0 * (double)d0 / (double)(n0 - 1);
+    double v = 0.0;
+    for (int r = 0; r <= ib; ++r)
+        v += binom(ib, r) * ipow(sh, ib - r) * mom[(size_t)(ia + r) * nitem + item];
+    const int lo = d0 > 0 ? n0 - d0 : 0, hi = d0 > 0 ? n0 : -d0;
+    for (int x0 = lo; x0 < hi; ++x0) {
+        const double c = coord<double>(x0, n0);
+        const double tor = coord<double>(imod(x0 + d0, n0), n0);
+        v += vrow[(size_t)x0 * nitem + item] * ipow(c, ia) * (ipow(tor, ib) - ipow(c + sh, ib));
     }
+    pi[idx] = v;
 }
 
 // 1-D sums sig0[ab][a][d0] = sum_x0 c0((x0-d0) mod N0)^ab c0(x0)^a (and the
@@ -274,10 +308,20 @@ hipError_t launch_polyrow(const Geom& g, const Tin* img, int da, int dbb, int K1
 }
 
 hipError_t launch_polycorr(const Geom& g, const double* vrow, int da, int dbb, int K0, int K1,
-                           double* pi, hipStream_t st) {
+                           double* part, double* pi, hipStream_t st) {
     const int nta = (da + 1) * (da + 2) / 2, ntb = (dbb + 1) * (dbb + 2) / 2;
-    hipLaunchKernelGGL(polycorr_kernel, dim3(nta * ntb * (2 * K0 + 1)), dim3(256), 0, st, g, vrow,
-                       da, dbb, K0, K1, pi);
+    const int nitem = (da + 1) * (dbb + 1) * (2 * K1 + 1);
+    const int ne = da + dbb + 1;
+    const int nchunk = (g.n0 + kRowChunk - 1) / kRowChunk;
+    // part holds nchunk * ne * nitem partial moments, then ne * nitem sums
+    double* mom = part + (size_t)nchunk * ne * nitem;
+    hipLaunchKernelGGL(polymom_kernel, dim3(nchunk), dim3(256), 0, st, g, vrow, nitem, ne, part);
+    const int nval = ne * nitem;
+    hipLaunchKernelGGL(momsum_kernel, dim3((nval + 255) / 256), dim3(256), 0, st, nchunk, nval, part,
+                       mom);
+    const int nout = nta * ntb * (2 * K0 + 1) * (2 * K1 + 1);
+    hipLaunchKernelGGL(polycorr_kernel, dim3((nout + 255) / 256), dim3(256), 0, st, g, vrow, mom, da,
+                       dbb, K0, K1, pi);
     return hipGetLastError();
 }
 

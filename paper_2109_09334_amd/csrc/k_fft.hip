@@ -114,13 +114,15 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
     }
 }
 
-// D(x0, .) = (1/N1) IDFT_row[Dt(x0, .)] - B(x0, .): two rows per packed
-// complex line (Hermitian extension of each half spectrum).
+// D(x0, .) = (1/N1) IDFT_row[Dt(x0, .)] - sky(x0, .): two rows per packed
+// complex line (Hermitian extension of each half spectrum). sky is the FP64
+// table of sky_kernel: sum_r c0(x0)^r Y_r(x1) on rows w0 <= x0 < N0 - w0,
+// tabulated rows on the 2 w0 edge rows.
 template <typename T, typename Tout>
 __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
                                                       const cx<T>* __restrict__ Dt,
                                                       Tout* __restrict__ d,
-                                                      const double* __restrict__ bcoef,
+                                                      const double* __restrict__ sky,
                                                       const cx<T>* __restrict__ tw) {
     cx<T>* lds = lds_base<T>();
     const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
@@ -151,19 +153,28 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
     line_fft<1, T>(buf, lp, lt, tw);
     if (act) {
         const double inv = 1.0 / (double)n1;
-        const double ca = coord<double>(xa, g.n0), cb = coord<double>(xb, g.n0);
+        const int n0 = g.n0, w0 = g.w0, R = max(g.dk, g.db);
+        const double ca = coord<double>(xa, n0), cb = coord<double>(xb, n0);
+        // edge rows read their own table row; interior rows the c0 powers
+        const double* ra = (xa < w0 || xa >= n0 - w0)
+                               ? sky + (size_t)(R + 1 + (xa < w0 ? xa : xa - n0 + 2 * w0)) * n1
+                               : nullptr;
+        const double* rb = (xb < w0 || xb >= n0 - w0)
+                               ? sky + (size_t)(R + 1 + (xb < w0 ? xb : xb - n0 + 2 * w0)) * n1
+                               : nullptr;
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) {
             const int x1 = lt + e * lp.tl;
-            const double c1 = coord<double>(x1, n1);
-            double ba = 0.0, bb = 0.0;
-            for (int m = 0; m < g.Q; ++m) {
-                int p, q;
-                term_ij(g.db, m, p, q);
-                const double t = bcoef[m] * ipow(c1, q);
-                ba += t * ipow(ca, p);
-                bb += t * ipow(cb, p);
+            double ba = 0.0, bb = 0.0, pa = 1.0, pb = 1.0;
+            for (int r = 0; r <= R; ++r) {
+                const double y = sky[(size_t)r * n1 + x1];
+                ba += pa * y;
+                bb += pb * y;
+                pa *= ca;
+                pb *= cb;
             }
+            if (ra) ba = ra[x1];
+            if (rb) bb = rb[x1];
             const cx<T> v = buf[x1];
             d[(size_t)xa * n1 + x1] = Tout((double)v.re * inv - ba);
             d[(size_t)xb * n1 + x1] = Tout((double)v.im * inv - bb);
@@ -227,13 +238,13 @@ hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs,
 
 template <typename T, typename Tout>
 hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, Tout* d,
-                         const double* bcoef, const cx<T>* tw, hipStream_t st) {
+                         const double* sky, const cx<T>* tw, hipStream_t st) {
     const size_t lds = (size_t)lp.lpw * lp.n * sizeof(cx<T>);
     auto k = rowinv_kernel<T, Tout>;
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     dim3 grid((g.n0 / 2 + lp.lpw - 1) / lp.lpw);
-    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, Dt, d, bcoef, tw);
+    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, Dt, d, sky, tw);
     return hipGetLastError();
 }
 

@@ -9,7 +9,9 @@
 //               sum_i Kt_(i,j)(a0, m) c0(x0 - a0)^i,
 //   Kt_k(a0, m) = sum_a1 kappa_k(a0, a1) W_N1^(m a1),
 // a (2 w0 + 1)-tap stencil along x0 per column m; the row inverse (k_fft)
-// then gives D and subtracts the background polynomial.
+// then gives D and subtracts the smooth FP64 part tabulated by sky_kernel
+// (the background polynomial and, when the transforms ran on the pedestal-
+// free pair R - c_R, S - c_S, the pedestal terms c_R (1 o K) - c_S).
 #include "kernels.hpp"
 
 namespace sfft {
@@ -69,21 +71,94 @@ __global__ void __launch_bounds__(256) stamp_spectra_kernel(Geom g, const double
     Kt[(size_t)row * g.hp + m] = mk(T(re), T(im));
 }
 
-// Row spectra of the weights: Y_j(m) = sum_x1 c1(x1)^j W_N1^(m x1), so the
-// row spectrum of c1^j (R' + c_R) is Z'_j + c_R Y_j (and Y_0 = N1 delta_m0).
-__global__ void __launch_bounds__(256) ytab_kernel(Geom g, const double* __restrict__ twp,
-                                                    cx<double>* __restrict__ ytab) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (m >= g.h) return;
-    double re = 0.0, im = 0.0;
-    for (int x1 = 0; x1 < g.n1; ++x1) {
-        const double c = ipow(coord<double>(x1, g.n1), j);
-        const int idx = (int)(((long long)m * x1) % g.n1);
-        re += c * twp[2 * idx];
-        im -= c * twp[2 * idx + 1];
+// Smooth part of the difference image, in FP64:
+//   sky(x) = B(x) + c_R V(x) - c_S,
+//   V(x) = sum_k sum_a kappa_k(a) T^k((x - a) mod N)   (V = 1 o K, Eq. 12),
+// so that D = IDFT[Dt] - sky with Dt from the pedestal-free spectra (c_R =
+// c_S = 0 when the transforms ran on R and S themselves: sky = B). Rows
+// w0 <= x0 < N0 - w0 see no wrap along axis 0, where c0(x0 - a0) =
+// c0(x0) + s_a0 with s_a0 = -2 a0 / (N0 - 1); there
+//   sky(x0, x1) = sum_r c0(x0)^r Y_r(x1),
+// and the 2 w0 edge rows (0..w0-1, N0-w0..N0-1) are tabulated as they are.
+// Every table row rho is a 1-D correlation along axis 1,
+//   c_R sum_k sum_a1 kappa'_(rho,k)(a1) c1((x1 - a1) mod N1)^(j_k) + (B, c_S terms),
+//   kappa'_(rho,k)(a1) = sum_a0 omega_rho(a0, i_k) kappa_k(a0, a1),
+// omega_r(a0, i) = C(i, r) s_a0^(i-r) (r <= i) for Y_r, and
+// omega_e(a0, i) = c0((x0_e - a0) mod N0)^i for edge row e.
+// Table: sky[r][x1] for r <= max(DK, DB), then edge row e at
+// sky[max(DK, DB) + 1 + e][x1].
+__global__ void __launch_bounds__(256) sky_stamps_kernel(Geom g, const double* __restrict__ kap,
+                                                          double* __restrict__ kap1) {
+    const int rho = blockIdx.x;
+    const int R = max(g.dk, g.db);
+    const int L = g.L0 * g.L1;
+    for (int t = threadIdx.x; t < g.P * g.L1; t += blockDim.x) {
+        const int k = t / g.L1, b = t % g.L1;
+        int i, j;
+        term_ij(g.dk, k, i, j);
+        double v = 0.0;
+        for (int a0 = -g.w0; a0 <= g.w0; ++a0) {
+            double om;
+            if (rho <= R) {
+                om = rho <= i ? binom(i, rho) * ipow(-2.0 * (double)a0 / (double)(g.n0 - 1), i - rho)
+                              : 0.0;
+            } else {
+                const int e = rho - R - 1;
+                const int x0 = e < g.w0 ? e : g.n0 - 2 * g.w0 + e;
+                om = ipow(coord<double>(imod(x0 - a0, g.n0), g.n0), i);
+            }
+            v += om * kap[(size_t)k * L + (a0 + g.w0) * g.L1 + b];
+        }
+        kap1[((size_t)rho * g.P + k) * g.L1 + b] = v;
     }
-    ytab[(size_t)j * g.h + m] = cx<double>{re, im};
+}
+
+constexpr int kSkyThreads = 64;
+
+__global__ void __launch_bounds__(kSkyThreads) sky_kernel(Geom g, const double* __restrict__ kap1,
+                                                          const double* __restrict__ bcoef,
+                                                          const double* __restrict__ ped,
+                                                          double* __restrict__ sky) {
+    const int x1 = blockIdx.x * kSkyThreads + threadIdx.x;
+    const int rho = blockIdx.y;
+    if (x1 >= g.n1) return;
+    const int n1 = g.n1, w1 = g.w1;
+    const int R = max(g.dk, g.db);
+    const double cR = ped ? ped[0] : 0.0, cS = ped ? ped[1] : 0.0;
+    double v = 0.0;
+    if (cR != 0.0) {
+        const double* kr = kap1 + (size_t)rho * g.P * g.L1;
+        for (int b = -w1; b <= w1; ++b) {
+            const double c = coord<double>(imod(x1 - b, n1), n1);
+            double pw[kMaxDegree + 1];
+            pw[0] = 1.0;
+#pragma unroll
+            for (int e = 1; e <= kMaxDegree; ++e) pw[e] = pw[e - 1] * c;
+            for (int k = 0; k < g.P; ++k) {
+                int i, j;
+                term_ij(g.dk, k, i, j);
+                double pj = pw[0];
+#pragma unroll
+                for (int e = 1; e <= kMaxDegree; ++e)
+                    if (e == j) pj = pw[e];
+                v += kr[(size_t)k * g.L1 + b + w1] * pj;
+            }
+        }
+        v *= cR;
+    }
+    const double c1 = coord<double>(x1, n1);
+    const bool edge = rho > R;
+    const int e = rho - R - 1;
+    const double c0 = edge ? coord<double>(e < g.w0 ? e : g.n0 - 2 * g.w0 + e, g.n0) : 0.0;
+    for (int m = 0; m < g.Q; ++m) {
+        int p, q;
+        term_ij(g.db, m, p, q);
+        const double t = bcoef[m] * ipow(c1, q);
+        if (edge) v += t * ipow(c0, p);
+        else if (p == rho) v += t;
+    }
+    if (edge || rho == 0) v -= cS;
+    sky[(size_t)rho * n1 + x1] = v;
 }
 
 // Tile: 64 columns x kStTile rows per block of 256 threads (4 row groups of
@@ -98,8 +173,6 @@ constexpr int kStTile = 4 * kStRows;
 template <typename T>
 __global__ void __launch_bounds__(256) stencil_kernel(Geom g, const cx<T>* __restrict__ Z, int zs,
                                                        const cx<T>* __restrict__ Kt,
-                                                       const double* __restrict__ ped,
-                                                       const cx<double>* __restrict__ ytab,
                                                        cx<T>* __restrict__ Dt) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int nsrc = kStTile + 2 * g.w0;
@@ -111,7 +184,6 @@ __global__ void __launch_bounds__(256) stencil_kernel(Geom g, const cx<T>* __res
     const int n0 = g.n0;
     const bool mok = m < g.h;
     const size_t plane = (size_t)n0 * g.hp;
-    const double cR = ped ? ped[0] : 0.0;
     for (int r = threadIdx.x; r < nsrc; r += blockDim.x)
         ct[r] = coord<T>(imod(x0b - g.w0 + r, n0), n0);
     cx<T> acc[kStRows];
@@ -119,22 +191,14 @@ __global__ void __launch_bounds__(256) stencil_kernel(Geom g, const cx<T>* __res
     for (int o = 0; o < kStRows; ++o) {
         const int x0 = x0b + rg * kStRows + o;
         acc[o] = mk(T(0), T(0));
-        if (mok && x0 < n0) {
-            acc[o] = Z[(size_t)zs * plane + (size_t)x0 * g.hp + m];
-            if (ped && m == 0) acc[o].re += T(ped[1] * (double)g.n1);
-        }
+        if (mok && x0 < n0) acc[o] = Z[(size_t)zs * plane + (size_t)x0 * g.hp + m];
     }
     for (int j = 0; j <= g.dk; ++j) {
         __syncthreads();
         const cx<T>* Zj = Z + (size_t)j * plane;
-        cx<T> add = mk(T(0), T(0));
-        if (ped && mok) {
-            const cx<double> y = ytab[(size_t)j * g.h + m];
-            add = mk(T(cR * y.re), T(cR * y.im));
-        }
         for (int r = rg; r < nsrc; r += 4) {
             const int xs = imod(x0b - g.w0 + r, n0);
-            zt[r * kStCols + mc] = mok ? Zj[(size_t)xs * g.hp + m] + add : mk(T(0), T(0));
+            zt[r * kStCols + mc] = mok ? Zj[(size_t)xs * g.hp + m] : mk(T(0), T(0));
         }
         __syncthreads();
         const int ni = g.dk - j;   // polynomial degree in c0 for this j
@@ -186,8 +250,8 @@ hipError_t launch_stamp_spectra(const Geom& g, const double* kap, const double* 
 }
 
 template <typename T>
-hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<T>* Kt,
-                          const double* ped, const cx<double>* ytab, cx<T>* Dt, hipStream_t st) {
+hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<T>* Kt, cx<T>* Dt,
+                          hipStream_t st) {
     const size_t nsrc = kStTile + 2 * g.w0;
     const size_t lds = nsrc * kStCols * sizeof(cx<T>) + nsrc * sizeof(T);
     if (lds > 65536) {
@@ -196,12 +260,17 @@ hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(stencil_kernel<T>, dim3((g.h + kStCols - 1) / kStCols, (g.n0 + kStTile - 1) / kStTile),
-                       dim3(256), lds, st, g, Z, zs_index, Kt, ped, ytab, Dt);
+                       dim3(256), lds, st, g, Z, zs_index, Kt, Dt);
     return hipGetLastError();
 }
 
-hipError_t launch_ytab(const Geom& g, const double* twp, cx<double>* ytab, hipStream_t st) {
-    hipLaunchKernelGGL(ytab_kernel, dim3((g.h + 255) / 256, g.dk + 1), dim3(256), 0, st, g, twp, ytab);
+hipError_t launch_sky(const Geom& g, const double* kap, const double* bcoef, const double* ped,
+                      double* kap1, double* sky, hipStream_t st) {
+    if (g.dk > kMaxDegree || g.db > kMaxDegree) return hipErrorInvalidValue;
+    const int nrho = max(g.dk, g.db) + 1 + 2 * g.w0;
+    if (ped) hipLaunchKernelGGL(sky_stamps_kernel, dim3(nrho), dim3(256), 0, st, g, kap, kap1);
+    hipLaunchKernelGGL(sky_kernel, dim3((g.n1 + kSkyThreads - 1) / kSkyThreads, nrho),
+                       dim3(kSkyThreads), 0, st, g, kap1, bcoef, ped, sky);
     return hipGetLastError();
 }
 
@@ -210,9 +279,8 @@ template hipError_t launch_stamp_spectra<float>(const Geom&, const double*, cons
 template hipError_t launch_stamp_spectra<double>(const Geom&, const double*, const double*,
                                                  cx<double>*, hipStream_t);
 template hipError_t launch_stencil<float>(const Geom&, const cx<float>*, int, const cx<float>*,
-                                          const double*, const cx<double>*, cx<float>*, hipStream_t);
+                                          cx<float>*, hipStream_t);
 template hipError_t launch_stencil<double>(const Geom&, const cx<double>*, int, const cx<double>*,
-                                           const double*, const cx<double>*, cx<double>*,
-                                           hipStream_t);
+                                           cx<double>*, hipStream_t);
 
 }  // namespace sfft

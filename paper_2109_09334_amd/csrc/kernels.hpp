@@ -37,7 +37,7 @@ hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs,
                          cx<T>* X, const cx<T>* tw, hipStream_t st);
 template <typename T, typename Tout>
 hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, Tout* d,
-                         const double* bcoef, const cx<T>* tw, hipStream_t st);
+                         const double* sky, const cx<T>* tw, hipStream_t st);
 template <typename T>
 hipError_t launch_fft_lines(const LinePlan& lp, int nlines, int sign, const cx<T>* in, cx<T>* out,
                             const cx<T>* tw, hipStream_t st);
@@ -56,8 +56,14 @@ hipError_t launch_lagrow(const Geom& g, int p0, int p1, const cx<T>* Cl, const d
 template <typename Tin>
 hipError_t launch_polyrow(const Geom& g, const Tin* img, int da, int dbb, int K1, double* vrow,
                           hipStream_t st);
+// part: scratch of polycorr_part_len(g, da, dbb, K1) doubles.
 hipError_t launch_polycorr(const Geom& g, const double* vrow, int da, int dbb, int K0, int K1,
-                           double* pi, hipStream_t st);
+                           double* part, double* pi, hipStream_t st);
+inline size_t polycorr_part_len(const Geom& g, int da, int dbb, int K1) {
+    const size_t nitem = (size_t)(da + 1) * (dbb + 1) * (2 * K1 + 1);
+    const size_t ne = da + dbb + 1;
+    return ((size_t)(g.n0 + 63) / 64 + 1) * ne * nitem;
+}
 hipError_t launch_polysum(const Geom& g, int dmax, double* sig0, double* sig1, double* pw,
                           hipStream_t st);
 hipError_t launch_pedestal(const Geom& g, const double* piR, int dmax, const double* piS,
@@ -73,10 +79,15 @@ hipError_t launch_gather(const Geom& g, const double* om, const double* th, cons
 // Cholesky of the Jacobi-scaled normal matrix and triangular solves.
 hipError_t launch_jacobi(int n, const double* G, const double* h, double* L, double* dsc,
                          double* rhs, int* flag, hipStream_t st);
-// dfac: scratch of ceil(n/64) * 64 * 64 doubles for the panels' diagonal factors.
-hipError_t launch_cholesky(int n, double* L, double* dfac, int* flag, hipStream_t st);
-hipError_t launch_chol_solve(int n, const double* L, const double* dsc, double* rhs,
-                             double* coef, int accumulate, const int* flag, hipStream_t st);
+// dfac: scratch of ceil(n/64) * 64 * 64 doubles for the panels' diagonal
+// factors; dinv: ceil(n/64) * 2 * 64 * 64 doubles, the inverses of the
+// diagonal blocks and their transposes (read by launch_chol_solve). L ends
+// with the factor in its lower and its transpose in its upper triangle.
+hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* flag,
+                           hipStream_t st);
+hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const double* dsc,
+                             double* rhs, double* coef, int accumulate, const int* flag,
+                             hipStream_t st);
 hipError_t launch_clear_flag(int* flag, hipStream_t st);
 
 // Subtraction.
@@ -84,11 +95,14 @@ hipError_t launch_stamps(const Geom& g, const double* coef, double* kap, hipStre
 template <typename T>
 hipError_t launch_stamp_spectra(const Geom& g, const double* kap, const double* twp, cx<T>* Kt,
                                 hipStream_t st);
-// ped (nullable): pedestals (c_R, c_S) removed from the row spectra in Z;
-// ytab: row spectra of the weights c1^j, [DK+1][h] FP64 complex.
+// Dt = Z_S - sum_k (R^k o kappa_k) in row-spectral form (no background).
 template <typename T>
-hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<T>* Kt,
-                          const double* ped, const cx<double>* ytab, cx<T>* Dt, hipStream_t st);
-hipError_t launch_ytab(const Geom& g, const double* twp, cx<double>* ytab, hipStream_t st);
+hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<T>* Kt, cx<T>* Dt,
+                          hipStream_t st);
+// sky[max(DK,DB) + 1 + 2 w0][n1]: smooth FP64 part of D (background and,
+// with ped, the pedestal terms c_R (1 o K) - c_S); ped may be null.
+// kap1: scratch of (max(DK,DB) + 1 + 2 w0) * P * L1 doubles.
+hipError_t launch_sky(const Geom& g, const double* kap, const double* bcoef, const double* ped,
+                      double* kap1, double* sky, hipStream_t st);
 
 }  // namespace sfft

@@ -38,13 +38,13 @@ struct Workspace {
     void* Kt = nullptr;     // [P][L0][hp]       stamp spectra along axis 1
     void* dfit = nullptr;   // [n0][n1]          IR difference image (compute type)
     double *omega, *theta, *thetaD, *lam, *cmat, *evec, *evecD;
-    double *vrow, *kap;
+    double *vrow, *vpart, *kap;
     double *piR, *piS, *piD;   // poly-correlation tables of R (|d| <= 2w), S and D (|d| <= w)
     double *sig0, *sig1, *pw;  // 1-D polynomial sums
     double* ped;               // pedestals c_R, c_S
-    cx<double>* ytab;          // row spectra of c1^j, [DK+1][h]
-    bool ytab_ready;
-    double *G, *h, *L, *dsc, *rhs, *coef, *dfac;
+    double* sky;               // smooth part of D: [max(DK,DB) + 1 + 2 w0][n1]
+    double* kap1;              // its 1-D stamps: [max(DK,DB) + 1 + 2 w0][P][L1]
+    double *G, *h, *L, *dsc, *rhs, *coef, *dfac, *dinv;
     int* flag;
 };
 
@@ -68,6 +68,7 @@ inline size_t carve(Workspace& w, const Geom& g, size_t cxb, size_t reb, char* b
     w.evec = c.take<double>(base, g.Q);
     w.evecD = c.take<double>(base, g.Q);
     w.vrow = c.take<double>(base, (size_t)g.n0 * (g.dk + 1) * (dm + 1) * g.D1);
+    w.vpart = c.take<double>(base, polycorr_part_len(g, g.dk, dm, 2 * g.w1));
     w.kap = c.take<double>(base, (size_t)g.P * g.L0 * g.L1);
     w.piR = c.take<double>(base, (size_t)g.P * ntb * g.D0 * g.D1);
     w.piS = c.take<double>(base, (size_t)ntb * g.L0 * g.L1);
@@ -76,7 +77,8 @@ inline size_t carve(Workspace& w, const Geom& g, size_t cxb, size_t reb, char* b
     w.sig1 = c.take<double>(base, (size_t)(g.dk + 1) * (g.dk + 1) * g.D1);
     w.pw = c.take<double>(base, 2 * (2 * dm + 1));
     w.ped = c.take<double>(base, 4);
-    w.ytab = c.take<cx<double>>(base, (size_t)(g.dk + 1) * g.h);
+    w.sky = c.take<double>(base, (size_t)(dm + 1 + 2 * g.w0) * g.n1);
+    w.kap1 = c.take<double>(base, (size_t)(dm + 1 + 2 * g.w0) * g.P * g.L1);
     w.G = c.take<double>(base, (size_t)g.nu * g.nu);
     w.h = c.take<double>(base, g.nu);
     w.L = c.take<double>(base, (size_t)g.nu * g.nu);
@@ -84,8 +86,8 @@ inline size_t carve(Workspace& w, const Geom& g, size_t cxb, size_t reb, char* b
     w.rhs = c.take<double>(base, g.nu);
     w.coef = c.take<double>(base, g.nu);
     w.dfac = c.take<double>(base, (size_t)((g.nu + 63) / 64) * 64 * 64);
+    w.dinv = c.take<double>(base, (size_t)((g.nu + 63) / 64) * 2 * 64 * 64);
     w.flag = c.take<int>(base, 64);
-    w.ytab_ready = false;
     return c.off + 256;
 }
 
