@@ -52,16 +52,23 @@ def load_pair(n, nstars):
 
 def stage_work(g, stage, s_cx):
     """Algorithmic (bytes, flops) of one call of a stage; s_cx = bytes per
-    complex value. FFT flops use the 5 N log2 N convention."""
+    complex value of the transforms. FFT flops use the 5 N log2 N convention;
+    the bytes count each input read once and each output written once."""
     n0, n1, w, dk, db = g["n0"], g["n1"], g["w"], g["dk"], g["db"]
     P = (dk + 1) * (dk + 2) // 2
+    Q = (db + 1) * (db + 2) // 2
     H = n1 // 2 + 1
     nr = dk + 2
     npair = P * (P + 1) // 2
     nprod = npair + P
     n = n0 * n1
+    L = 2 * w + 1
+    nu = P * L * L + Q
     fft = lambda N: 5.0 * N * math.log2(N)
-    if stage == "rowfwd":
+    if stage == "background":      # FP64 poly-correlation tables: one pass over R and S
+        by = 2 * 4 * n
+        fl = n * 2.0 * (2 * dk + 2 + (dk + 1) * (dk + 1) * (4 * w + 1))
+    elif stage == "rowfwd":
         by = 2 * 4 * n + nr * n0 * H * s_cx
         fl = n0 * math.ceil(nr / 2) * fft(n1)
     elif stage == "colfwd":
@@ -73,6 +80,15 @@ def stage_work(g, stage, s_cx):
     elif stage == "lagrow":
         by = nprod * (4 * w + 1) * H * s_cx
         fl = nprod * (4 * w + 1) * H * 2.0 * (4 * w + 1)
+    elif stage == "gather":
+        by = 8.0 * (nu * nu + nu)
+        fl = 0.0
+    elif stage == "cholesky":      # Jacobi scaling + factor of the N_u x N_u FP64 matrix
+        by = 8.0 * 2 * nu * nu
+        fl = nu ** 3 / 3.0
+    elif stage == "trsv":          # both sweeps read the factor once
+        by = 8.0 * nu * nu
+        fl = 2.0 * nu * nu
     elif stage == "stencil":
         by = (nr + 1) * n0 * H * s_cx
         fl = n0 * H * 8.0 * P * (2 * w + 1)
@@ -82,6 +98,18 @@ def stage_work(g, stage, s_cx):
     else:
         return None
     return by, fl
+
+
+def roofline(stage, ms, wk):
+    by, fl = wk
+    gbs = by / (ms * 1e-3) / 1e9
+    tfl = fl / (ms * 1e-3) / 1e12
+    f_h, f_a = gbs / HBM_PEAK_GBS, tfl / ALU_PEAK_TFLOPS
+    if f_a > f_h:
+        return {"bound": "alu", "achieved": tfl, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": f_a, "kernel": stage, "kernel_ms": ms, "hbm_frac": f_h}
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": f_h, "kernel": stage, "kernel_ms": ms, "alu_frac": f_a}
 
 
 def main():
@@ -214,32 +242,23 @@ def main():
     st_m = stages(pm)
     st_64 = stages(p64) if not args.no_fp64 else None
     geo = {"n0": n, "n1": n, "w": w, "dk": dk, "db": db}
-    best = None
+    # every stage against its own roofline (algorithmic bytes / flops per call
+    # over the HIP-event time of the call); the reported roofline is that of
+    # the stage with the largest time per pair
+    stage_roof = {}
     for name, ms in st_m.items():
         wk = stage_work(geo, name, 8)
-        if wk is None:
-            continue
-        by, fl = wk
-        gbs = by / (ms * 1e-3) / 1e9
-        tfl = fl / (ms * 1e-3) / 1e12
-        f_h, f_a = gbs / HBM_PEAK_GBS, tfl / ALU_PEAK_TFLOPS
-        cand = {"stage": name, "ms": ms, "gbs": gbs, "tflops": tfl, "frac_hbm": f_h, "frac_alu": f_a}
-        if best is None or ms > best["ms"]:
-            best = cand
-    if best["frac_alu"] >= best["frac_hbm"]:
-        roof = {"bound": "alu", "achieved": best["tflops"], "peak": ALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": best["frac_alu"], "traffic": None}
-    else:
-        roof = {"bound": "hbm", "achieved": best["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": best["frac_hbm"], "traffic": None}
-    roof["kernel"] = best["stage"]
-    roof["kernel_ms"] = best["ms"]
+        if wk is not None:
+            stage_roof[name] = roofline(name, ms, wk)
+    dom = max(stage_roof.values(), key=lambda r: r["kernel_ms"])
+    roof = dict(dom)
+    roof["traffic"] = None
 
     # ---- CPU baseline: the FP64 oracle on a bounded crop of the same pair
     cpu = None
     if not args.no_cpu:
         import oracle
-        crop = int(os.environ.get("SFFT_BENCH_CPU_CROP", "1024"))
+        crop = int(os.environ.get("SFFT_BENCH_CPU_CROP", "2048"))
         rc = np.ascontiguousarray(r_np[:crop, :crop], dtype=np.float64)
         sc = np.ascontiguousarray(s_np[:crop, :crop], dtype=np.float64)
         t = time.perf_counter()
@@ -276,6 +295,7 @@ def main():
         "fp64_form": res64,
         "stages_ms": {"mixed": st_m, "fp64": st_64},
         "roofline": roof,
+        "stage_roofline": stage_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

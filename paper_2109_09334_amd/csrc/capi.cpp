@@ -84,21 +84,42 @@ static Geom make_geom(const sfft_params* p) {
     return g;
 }
 
+// Radix order: 16 first (the first pass runs on the registers as loaded),
+// then the small radices, then the remaining 16s (a radix-16 last pass ends in
+// registers in natural order).
 static LinePlan make_line_plan(int n) {
     LinePlan lp{};
     lp.n = n;
     int a, b;
     radix23(n, &a, &b);
     int np = 0;
-    while (a >= 4) { lp.radix[np++] = 16; a -= 4; }
-    if (a == 3) lp.radix[np++] = 8;
-    else if (a == 2) lp.radix[np++] = 4;
-    else if (a == 1) lp.radix[np++] = 2;
+    lp.radix[np++] = 16;
+    a -= 4;
+    const int n16 = a / 4, rem = a % 4;
+    if (rem) lp.radix[np++] = 1 << rem;
     while (b-- > 0) lp.radix[np++] = 3;
+    for (int i = 0; i < n16; ++i) lp.radix[np++] = 16;
     lp.npass = np;
+    int off = 0, ns = 1;
+    for (int p = 0; p < np; ++p) {
+        lp.twoff[p] = off;
+        if (p > 0) off += ns * 16;
+        ns *= lp.radix[p];
+    }
     lp.tl = n / kElemsPerThread;
     lp.lpw = lp.tl >= 256 ? 1 : 256 / lp.tl;
     return lp;
+}
+
+// Entries of the pass twiddle tables of make_line_plan(n).
+static int pass_table_len(int n) {
+    const LinePlan lp = make_line_plan(n);
+    int len = 0, ns = 1;
+    for (int p = 0; p < lp.npass; ++p) {
+        if (p > 0) len += ns * 16;
+        ns *= lp.radix[p];
+    }
+    return len;
 }
 
 size_t workspace_bytes(const sfft_params* p) {
@@ -108,32 +129,45 @@ size_t workspace_bytes(const sfft_params* p) {
     return carve(w, g, mixed ? 8 : 16, mixed ? 4 : 8, nullptr);
 }
 
+template <typename T>
+static hipError_t upload(const std::vector<cx<double>>& v, void** dst) {
+    std::vector<cx<T>> h(v.size());
+    for (size_t i = 0; i < v.size(); ++i) h[i] = {(T)v[i].re, (T)v[i].im};
+    hipError_t e = hipMalloc(dst, h.size() * sizeof(cx<T>));
+    if (e) return e;
+    return hipMemcpy(*dst, h.data(), h.size() * sizeof(cx<T>), hipMemcpyHostToDevice);
+}
+
+// Twiddles of length n: the full table W_n^t = e^(-2 pi i t / n), the pass
+// tables of the line plan (pass p: row k holds W_(ns R)^(r k), r < R, in 16
+// entries, ns = product of the earlier radices), and the FP64 cos / sin
+// pairs. Angles in long double, rounded once to the compute type.
 static hipError_t make_twiddles(int n, bool mixed, Twiddles& t) {
-    std::vector<double> c(n), s(n);
-    for (int k = 0; k < n; ++k) {
-        const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)k / (long double)n;
-        c[k] = (double)cosl(ang);
-        s[k] = (double)sinl(ang);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    auto W = [&](long long num, long long den) {
+        const long double ang = two_pi * (long double)(num % den) / (long double)den;
+        return cx<double>{(double)cosl(ang), (double)-sinl(ang)};
+    };
+    std::vector<cx<double>> full(n);
+    for (int k = 0; k < n; ++k) full[k] = W(k, n);
+    const LinePlan lp = make_line_plan(n);
+    std::vector<cx<double>> pass(pass_table_len(n) + 16, cx<double>{0.0, 0.0});
+    int ns = 1;
+    for (int p = 0; p < lp.npass; ++p) {
+        const int R = lp.radix[p];
+        if (p > 0)
+            for (int k = 0; k < ns; ++k)
+                for (int r = 0; r < R; ++r) pass[lp.twoff[p] + (size_t)k * 16 + r] = W((long long)r * k, (long long)ns * R);
+        ns *= R;
     }
-    hipError_t e;
-    if (mixed) {
-        std::vector<cx<float>> v(n);
-        for (int k = 0; k < n; ++k) v[k] = {(float)c[k], (float)-s[k]};
-        e = hipMalloc(&t.tw, n * sizeof(cx<float>));
-        if (e) return e;
-        e = hipMemcpy(t.tw, v.data(), n * sizeof(cx<float>), hipMemcpyHostToDevice);
-    } else {
-        std::vector<cx<double>> v(n);
-        for (int k = 0; k < n; ++k) v[k] = {c[k], -s[k]};
-        e = hipMalloc(&t.tw, n * sizeof(cx<double>));
-        if (e) return e;
-        e = hipMemcpy(t.tw, v.data(), n * sizeof(cx<double>), hipMemcpyHostToDevice);
-    }
+    hipError_t e = mixed ? upload<float>(full, &t.tw) : upload<double>(full, &t.tw);
+    if (e) return e;
+    e = mixed ? upload<float>(pass, &t.twt) : upload<double>(pass, &t.twt);
     if (e) return e;
     std::vector<double> vp(2 * n);
     for (int k = 0; k < n; ++k) {
-        vp[2 * k] = c[k];
-        vp[2 * k + 1] = s[k];
+        vp[2 * k] = full[k].re;
+        vp[2 * k + 1] = -full[k].im;
     }
     e = hipMalloc(&t.twp, 2 * n * sizeof(double));
     if (e) return e;
@@ -142,6 +176,8 @@ static hipError_t make_twiddles(int n, bool mixed, Twiddles& t) {
 
 static void free_twiddles(Twiddles& t) {
     if (t.tw) (void)hipFree(t.tw);
+    if (t.twt) (void)hipFree(t.twt);
+    t.twt = nullptr;
     if (t.twp) (void)hipFree(t.twp);
     t.tw = nullptr;
     t.twp = nullptr;
@@ -270,7 +306,7 @@ static hipError_t forward_fit(Plan& pl, const Tin* r, const Tin* s, hipStream_t 
     {
         StageTimer t_(pl.prof, "rowfwd", st);
         e = launch_rowfwd<T, Tin>(g, pl.lp1, pair_sources(g, true), r, s, w.ped, cxp<T>(w.Z),
-                                  cxp<T>(pl.t1.tw), st);
+                                  cxp<T>(pl.t1.twt), st);
     }
     if (e) return e;
     ColJobs jobs{};
@@ -284,7 +320,7 @@ static hipError_t forward_fit(Plan& pl, const Tin* r, const Tin* s, hipStream_t 
     jobs.nw[g.dk + 1] = 1;
     jobs.spec[g.dk + 1][0] = g.P;
     StageTimer t_(pl.prof, "colfwd", st);
-    return launch_colfwd<T>(g, pl.lp0, jobs, cxp<T>(w.Z), cxp<T>(w.X), cxp<T>(pl.t0.tw), st);
+    return launch_colfwd<T>(g, pl.lp0, jobs, cxp<T>(w.Z), cxp<T>(w.X), cxp<T>(pl.t0.twt), st);
 }
 
 // Pedestal tables, transforms, products and pruned inverses, then the exact
@@ -297,7 +333,7 @@ static hipError_t lag_tables(Plan& pl, const Tin* r, const Tin* s, hipStream_t s
     if (!e) e = forward_fit<T, Tin>(pl, r, s, st);
     if (!e) {
         StageTimer t_(pl.prof, "lagcol", st);
-        e = launch_lagcol<T>(g, pl.lp0, 0, g.nprod, g.P, cxp<T>(w.X), cxp<T>(w.Cl), cxp<T>(pl.t0.tw), st);
+        e = launch_lagcol<T>(g, pl.lp0, 0, g.nprod, g.P, cxp<T>(w.X), cxp<T>(w.Cl), cxp<T>(pl.t0.tw), cxp<T>(pl.t0.twt), st);
     }
     if (!e) {
         StageTimer t_(pl.prof, "lagrow", st);
@@ -339,7 +375,7 @@ static hipError_t difference(Plan& pl, int zs, bool pedestal, const double* coef
     }
     if (!e) {
         StageTimer t_(pl.prof, "rowinv", st);
-        e = launch_rowinv<T, Tout>(g, pl.lp1, cxp<T>(w.Dt), d, w.sky, cxp<T>(pl.t1.tw), st);
+        e = launch_rowinv<T, Tout>(g, pl.lp1, cxp<T>(w.Dt), d, w.sky, cxp<T>(pl.t1.twt), st);
     }
     return e;
 }
@@ -357,8 +393,7 @@ static hipError_t factor_solve(Plan& pl, const double* G, const double* h, doubl
     }
     if (!e) {
         StageTimer t_(pl.prof, "trsv", st);
-        e = hipMemcpyAsync(w.rhs, h, n * sizeof(double), hipMemcpyDeviceToDevice, st);
-        if (!e) e = launch_chol_solve(n, w.L, w.dinv, w.dsc, w.rhs, coef, 0, w.flag, st);
+        e = launch_chol_solve(n, w.L, w.dinv, w.dsc, h, coef, 0, w.flag, st);
     }
     return e;
 }
@@ -389,14 +424,14 @@ static hipError_t refine(Plan& pl, double* coef, hipStream_t st) {
     src.img[0] = 0;
     src.out[0] = g.nr;
     src.ped[0] = -1;
-    if (!e) e = launch_rowfwd<T, T>(g, pl.lp1, src, dfit, dfit, w.ped, cxp<T>(w.Z), cxp<T>(pl.t1.tw), st);
+    if (!e) e = launch_rowfwd<T, T>(g, pl.lp1, src, dfit, dfit, w.ped, cxp<T>(w.Z), cxp<T>(pl.t1.twt), st);
     ColJobs jobs{};
     jobs.narr = 1;
     jobs.arr[0] = g.nr;
     jobs.nw[0] = 1;
     jobs.spec[0][0] = g.P + 1;
-    if (!e) e = launch_colfwd<T>(g, pl.lp0, jobs, cxp<T>(w.Z), cxp<T>(w.X), cxp<T>(pl.t0.tw), st);
-    if (!e) e = launch_lagcol<T>(g, pl.lp0, g.npair, g.nprod, g.P + 1, cxp<T>(w.X), cxp<T>(w.Cl), cxp<T>(pl.t0.tw), st);
+    if (!e) e = launch_colfwd<T>(g, pl.lp0, jobs, cxp<T>(w.Z), cxp<T>(w.X), cxp<T>(pl.t0.twt), st);
+    if (!e) e = launch_lagcol<T>(g, pl.lp0, g.npair, g.nprod, g.P + 1, cxp<T>(w.X), cxp<T>(w.Cl), cxp<T>(pl.t0.tw), cxp<T>(pl.t0.twt), st);
     if (!e) e = launch_lagrow<T>(g, g.npair, g.nprod, cxp<T>(w.Cl), pl.t1.twp, w.omega, w.thetaD, st);
     if (!e) e = launch_lagfix(g, 1, w.ped, w.piR, w.piD, w.sig0, w.sig1, w.pw, dm, nullptr,
                               w.thetaD, nullptr, nullptr, w.evecD, st);
@@ -441,7 +476,7 @@ static int run_subtract_t(Plan& pl, const void* r, const void* s, const double* 
     {
         StageTimer t_(pl.prof, "rowfwd", st);
         e = launch_rowfwd<T, Tin>(g, pl.lp1, pair_sources(g, false), (const Tin*)r, (const Tin*)s,
-                                  nullptr, cxp<T>(pl.ws.Z), cxp<T>(pl.t1.tw), st);
+                                  nullptr, cxp<T>(pl.ws.Z), cxp<T>(pl.t1.twt), st);
     }
     if (!e) e = difference<T, Tin>(pl, g.dk + 1, false, coef, (Tin*)d, st);
     return hip_status(e);
@@ -642,10 +677,10 @@ int sfft_fft_lines(sfft_ctx* ctx, int n, int lines, int sign, int dtype, const v
     hipError_t e;
     if (dtype == SFFT_F32)
         e = launch_fft_lines<float>(lp, lines, sign, (const cx<float>*)in, (cx<float>*)out,
-                                    (const cx<float>*)t.tw, (hipStream_t)stream);
+                                    (const cx<float>*)t.twt, (hipStream_t)stream);
     else
         e = launch_fft_lines<double>(lp, lines, sign, (const cx<double>*)in, (cx<double>*)out,
-                                     (const cx<double>*)t.tw, (hipStream_t)stream);
+                                     (const cx<double>*)t.twt, (hipStream_t)stream);
     return hip_status(e);
 }
 

@@ -45,6 +45,7 @@ struct LinePlan {
     int n;
     int npass;
     int radix[kMaxPass];
+    int twoff[kMaxPass];   // offset of pass p's twiddle table (pass tables)
     int tl;     // threads per line = n / kElemsPerThread
     int lpw;    // lines per workgroup
 };

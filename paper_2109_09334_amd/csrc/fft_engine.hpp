@@ -1,8 +1,9 @@
 // Line FFT engine for gfx950: a mixed-radix (2, 3, 4, 8, 16) Stockham
-// autosort transform of one line held in LDS, computed in place. Each pass
-// stages the thread's butterfly inputs in registers, synchronises, applies
-// the inter-pass twiddles and the radix-R DFT, and writes the results back
-// at their Stockham positions:
+// autosort transform of one line, 16 elements per thread. The first and (for
+// a radix-16 tail) last passes run on registers; the passes between stage the
+// thread's butterfly inputs from a padded LDS line, synchronise, apply the
+// inter-pass twiddles (per-pass tables) and the radix-R DFT, and write the
+// results back at their Stockham positions:
 //   inputs   v[r] = x[j + r N/R]                 (j = butterfly, r < R)
 //   twiddle  v[r] *= W_N^(r k N/(Ns R)),  k = j mod Ns, W_N = e^(S 2 pi i / N)
 //   outputs  y[(j / Ns) Ns R + k + r Ns] = DFT_R(v)[r]
@@ -109,22 +110,50 @@ struct Dft {
     }
 };
 
-// One Stockham pass of radix R over a line of n points at buf.
-// lt = thread index within the line, tl = threads per line.
-// tw = table of W_n^t = e^(-2 pi i t / n), t < n (conjugated for S > 0).
+// LDS index with one padding slot per 16 elements. The first pass writes
+// each thread's 16 outputs contiguously (a stride of 16 elements across the
+// lanes), which without padding maps every lane to the same few banks.
+__host__ __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int line_lds_elems(int n) { return n + (n >> 4); }
+
+// w[1..R-1] = row[1..R-1] (a twiddle row of the pass tables, 16 entries,
+// 16-entry aligned), conjugated for the inverse transform.
+template <int R, int S>
+__device__ __forceinline__ void load_twiddles(cx<float>* w, const cx<float>* __restrict__ row) {
+    const float4* q = reinterpret_cast<const float4*>(row);
+#pragma unroll
+    for (int h = 0; h < (R + 1) / 2; ++h) {
+        const float4 t = q[h];
+        w[2 * h] = cx<float>{t.x, S > 0 ? -t.y : t.y};
+        if (2 * h + 1 < R) w[2 * h + 1] = cx<float>{t.z, S > 0 ? -t.w : t.w};
+    }
+}
+template <int R, int S>
+__device__ __forceinline__ void load_twiddles(cx<double>* w, const cx<double>* __restrict__ row) {
+    const double2* q = reinterpret_cast<const double2*>(row);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        const double2 t = q[r];
+        w[r] = cx<double>{t.x, S > 0 ? -t.y : t.y};
+    }
+}
+
+// One Stockham pass of radix R (> the first) through the padded LDS line.
+// twt: the pass table, row k = W_(ns R)^(r k), r < 16.
 template <int R, int S, typename T>
-__device__ __forceinline__ void stockham_pass(cx<T>* buf, int n, int ns, int lt, int tl,
-                                              const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void pass_lds(cx<T>* buf, int n, int ns, int lt, int tl,
+                                         const cx<T>* __restrict__ twt) {
     constexpr int NB = (kElemsPerThread + R - 1) / R;
     const int nbf = n / R;
-    const int step = n / (ns * R);
-    cx<T> v[NB][R];
+    cx<T> v[NB][R], w[NB][R];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = lt + b * tl;
         if (j < nbf) {
+            const int k = j % ns;
+            load_twiddles<R, S>(w[b], twt + (size_t)k * 16);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * nbf];
+            for (int r = 0; r < R; ++r) v[b][r] = buf[lpad(j + r * nbf)];
         }
     }
     __syncthreads();
@@ -133,37 +162,61 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, int n, int ns, int lt,
         const int j = lt + b * tl;
         if (j < nbf) {
             const int k = j % ns;
-            const int tstep = k * step;
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                cx<T> w = tw[r * tstep];
-                if (S > 0) w.im = -w.im;
-                v[b][r] = cmul(v[b][r], w);
-            }
+            for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], w[b][r]);
             Dft<R, S, T>::run(v[b]);
             const int o = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[o + r * ns] = v[b][r];
+            for (int r = 0; r < R; ++r) buf[lpad(o + r * ns)] = v[b][r];
         }
     }
     __syncthreads();
 }
 
-// Full transform of the line at buf (all threads of the workgroup call it).
+// Transform of one line whose data stays in registers at both ends: on entry
+// v[e] = x[lt + e tl], on exit v[e] = X[lt + e tl] (natural order), e < 16.
+// The plan starts with radix 16, so the first pass runs on the registers as
+// loaded (Ns = 1, no twiddles); when it also ends with radix 16, the last
+// pass (Ns = n/16 = tl, butterfly j = lt) leaves its outputs in natural order
+// in the registers. The passes between go through the padded LDS line buf.
+// All threads of the workgroup call it (it synchronises); the caller must
+// not touch buf between a call and the next barrier.
 template <int S, typename T>
-__device__ __forceinline__ void line_fft(cx<T>* buf, const LinePlan& lp, int lt,
-                                         const cx<T>* __restrict__ tw) {
-    int ns = 1;
-    for (int p = 0; p < lp.npass; ++p) {
-        const int R = lp.radix[p];
-        switch (R) {
-            case 16: stockham_pass<16, S, T>(buf, lp.n, ns, lt, lp.tl, tw); break;
-            case 8: stockham_pass<8, S, T>(buf, lp.n, ns, lt, lp.tl, tw); break;
-            case 4: stockham_pass<4, S, T>(buf, lp.n, ns, lt, lp.tl, tw); break;
-            case 3: stockham_pass<3, S, T>(buf, lp.n, ns, lt, lp.tl, tw); break;
-            default: stockham_pass<2, S, T>(buf, lp.n, ns, lt, lp.tl, tw); break;
+__device__ __forceinline__ void line_fft_regs(cx<T>* v, cx<T>* buf, const LinePlan& lp, int lt,
+                                              const cx<T>* __restrict__ twt) {
+    Dft<16, S, T>::run(v);
+    if (lp.npass == 1) return;
+    const int n = lp.n, tl = lp.tl;
+    __syncthreads();   // buf may still be read by a previous transform
+#pragma unroll
+    for (int r = 0; r < 16; ++r) buf[lpad(16 * lt + r)] = v[r];
+    __syncthreads();
+    int ns = 16;
+    const int last = lp.npass - 1;
+    const bool tail16 = lp.radix[last] == 16;
+    const int pend = tail16 ? last : lp.npass;
+    for (int p = 1; p < pend; ++p) {
+        const cx<T>* tp = twt + lp.twoff[p];
+        switch (lp.radix[p]) {
+            case 16: pass_lds<16, S, T>(buf, n, ns, lt, tl, tp); break;
+            case 8: pass_lds<8, S, T>(buf, n, ns, lt, tl, tp); break;
+            case 4: pass_lds<4, S, T>(buf, n, ns, lt, tl, tp); break;
+            case 3: pass_lds<3, S, T>(buf, n, ns, lt, tl, tp); break;
+            default: pass_lds<2, S, T>(buf, n, ns, lt, tl, tp); break;
         }
-        ns *= R;
+        ns *= lp.radix[p];
+    }
+    if (tail16) {
+        cx<T> w[16];
+        load_twiddles<16, S>(w, twt + lp.twoff[last] + (size_t)lt * 16);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = buf[lpad(lt + r * tl)];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
+        Dft<16, S, T>::run(v);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = buf[lpad(lt + e * tl)];
     }
 }
 

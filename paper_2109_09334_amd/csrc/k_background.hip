@@ -13,8 +13,8 @@
 // explicit correction over the wrapped columns.
 //
 // Pedestal: the spectral path transforms R' = R - c_R and S' = S - c_S
-// (c = image means) so that FP32 FFT rounding scales with the fluctuations
-// and not with the sky level. The exact identities restore the full tables:
+// (c = image means, rounded to 8 significant bits) so that FP32 FFT rounding
+// scales with the fluctuations and not with the sky level. The exact identities restore the full tables:
 //   Omega_{kb k}(d) = Omega'(d) + c_R (Pi^R_{kb k}(d) + Pi^R_{k kb}(-d))
 //                     - c_R^2 C_{kb k}(d),  C(d) = sum_x T^kb(x-d) T^k(x)
 //   Theta_kb(d)     = Theta'(d) + c_S Pi^R_{kb 0}(0) + c_R Pi^S_{0 kb}(-d)
@@ -212,14 +212,25 @@ __global__ void __launch_bounds__(256) polysum_kernel(Geom g, int dmax, double* 
 }
 
 // Pedestals: image means from the (0, 0) entries of the poly tables.
+// The pedestal is the image mean rounded to 8 significant bits: subtracting
+// it from an FP32 pixel of at least its magnitude is then exact, so removing
+// it adds no rounding of its own to FP32 images (the identities above hold
+// for any constant).
+__device__ __forceinline__ double short_pedestal(double c) {
+    if (c == 0.0 || !isfinite(c)) return 0.0;
+    int e;
+    (void)frexp(c, &e);   // |c| = f 2^e, 0.5 <= f < 1
+    return ldexp(rint(ldexp(c, 8 - e)), e - 8);
+}
+
 __global__ void pedestal_kernel(Geom g, const double* __restrict__ piR, int ntbR, int K0R, int K1R,
                                 const double* __restrict__ piS, int ntbS, int K0S, int K1S,
                                 double* __restrict__ ped) {
     (void)ntbR;
     (void)ntbS;
     const double n = (double)g.n0 * (double)g.n1;
-    ped[0] = piR[(size_t)K0R * (2 * K1R + 1) + K1R] / n;
-    ped[1] = piS[(size_t)K0S * (2 * K1S + 1) + K1S] / n;
+    ped[0] = short_pedestal(piR[(size_t)K0R * (2 * K1R + 1) + K1R] / n);
+    ped[1] = short_pedestal(piS[(size_t)K0S * (2 * K1S + 1) + K1S] / n);
 }
 
 // Assemble the FP64 tables used by the gather:

@@ -55,7 +55,10 @@ __global__ void __launch_bounds__(256) scale_kernel(int n, const double* __restr
 // right-looking pass over the 64 columns: 256 threads own 4x4 register tiles
 // (rows ty + 16 a, columns tx + 16 b) of D and of A; the raw column j is
 // published through LDS (double buffered, so one barrier per column) and
-// every thread scales it by the pivot itself before its rank-1 update.
+// every thread scales it by the pivot itself before its rank-1 update. The
+// column group bj = j / 16 is a compile-time index (the loop over it is
+// unrolled), so the owners address their tile registers statically and the
+// updates skip the column groups left of the pivot.
 __global__ void __launch_bounds__(256) panel_kernel(int n, double* __restrict__ L, int kb,
                                                      double* __restrict__ dfac, int* flag) {
     __shared__ double colD[2][NBK];
@@ -73,68 +76,59 @@ __global__ void __launch_bounds__(256) panel_kernel(int n, double* __restrict__ 
             d[a][b] = (i < nb && c <= i) ? L[(size_t)(kb + i) * n + kb + c] : 0.0;
             x[a][b] = (i < nr && c < nb) ? L[(size_t)(r0 + i) * n + kb + c] : 0.0;
         }
-    for (int j = 0; j < nb; ++j) {
-        const int buf = j & 1, bj = j >> 4;
-        const bool owner = tx == (j & 15);
-        if (owner) {
-            // static register indexing (a runtime index would move the tiles
-            // to scratch memory)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+#pragma unroll 1
+        for (int jj = 0; jj < 16; ++jj) {
+            const int j = 16 * bj + jj;
+            if (j >= nb) break;   // uniform over the workgroup
+            const int buf = j & 1;
+            const bool owner = tx == jj;
+            if (owner) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    colD[buf][ty + 16 * a] = d[a][bj];
+                    colA[buf][ty + 16 * a] = x[a][bj];
+                }
+            }
+            __syncthreads();
+            // all LDS reads first (unconditional, so they issue together)
+            double cd[4], cx[4], cc[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
-                double vd = d[a][0], vx = x[a][0];
-#pragma unroll
-                for (int b = 1; b < 4; ++b)
-                    if (b == bj) {
-                        vd = d[a][b];
-                        vx = x[a][b];
-                    }
-                colD[buf][ty + 16 * a] = vd;
-                colA[buf][ty + 16 * a] = vx;
+                cd[a] = colD[buf][ty + 16 * a];
+                cx[a] = colA[buf][ty + 16 * a];
+                cc[a] = colD[buf][tx + 16 * a];
             }
-        }
-        __syncthreads();
-        // all LDS reads first (unconditional, so they issue together), then
-        // selects
-        double cd[4], cx[4], cc[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            cd[a] = colD[buf][ty + 16 * a];
-            cx[a] = colA[buf][ty + 16 * a];
-            cc[a] = colD[buf][tx + 16 * a];
-        }
-        double piv = colD[buf][j];
-        if (!(piv > 0.0) || !isfinite(piv)) {
-            if (threadIdx.x == 0) atomicOr(flag, isfinite(piv) ? kFlagNotSpd : kFlagNonFinite);
-            piv = 1.0;
-        }
-        const double ljj = sqrt(piv), inv = 1.0 / ljj;
-        double li[4], xi[4], lc[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            li[a] = ty + 16 * a > j ? cd[a] * inv : 0.0;
-            xi[a] = cx[a] * inv;
-            lc[a] = tx + 16 * a > j ? cc[a] * inv : 0.0;
-        }
-        if (owner) {
+            double piv = colD[buf][j];
+            if (!(piv > 0.0) || !isfinite(piv)) {
+                if (threadIdx.x == 0) atomicOr(flag, isfinite(piv) ? kFlagNotSpd : kFlagNonFinite);
+                piv = 1.0;
+            }
+            const double inv = rsqrt(piv), ljj = piv * inv;
+            double li[4], xi[4], lc[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
-                const int i = ty + 16 * a;
-                const double nd = i == j ? ljj : (i > j ? li[a] : 0.0);
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (b == bj) {
-                        d[a][b] = nd;
-                        x[a][b] = xi[a];
-                    }
+                li[a] = ty + 16 * a > j ? cd[a] * inv : 0.0;
+                xi[a] = cx[a] * inv;
+                lc[a] = tx + 16 * a > j ? cc[a] * inv : 0.0;
             }
+            if (owner) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int i = ty + 16 * a;
+                    d[a][bj] = i == j ? ljj : (i > j ? li[a] : 0.0);
+                    x[a][bj] = xi[a];
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = bj; b < 4; ++b) {
+                    d[a][b] -= li[a] * lc[b];
+                    x[a][b] -= xi[a] * lc[b];
+                }
         }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                d[a][b] -= li[a] * lc[b];
-                x[a][b] -= xi[a] * lc[b];
-            }
     }
     if (blockIdx.x == 0) {
         double* out = dfac + (size_t)(kb / NBK) * NBK * NBK;
@@ -159,43 +153,70 @@ __global__ void __launch_bounds__(256) panel_kernel(int n, double* __restrict__ 
 // After the last panel, per diagonal block B: the factor held in dfac goes
 // into L (lower part, with its transpose in the upper part of the tile), and
 // W_B = L_BB^-1 and W_B^T are stored in dinv[B][0] and dinv[B][1] (64 x 64
-// row-major, zero outside the triangle) for the triangular solves. One wave
-// per block; lane c computes column c of W by forward substitution.
-__global__ void __launch_bounds__(64) diag_finish_kernel(int n, double* __restrict__ L,
-                                                          const double* __restrict__ dfac,
-                                                          double* __restrict__ dinv) {
+// row-major, zero outside the triangle) for the triangular solves. W comes
+// from L W = I by a right-looking sweep over the rows: row j of W is the
+// current row j of the right-hand side divided by L_jj, then every row i > j
+// loses L_ij times it. 256 threads own 4x4 tiles (rows ty + 16 a, columns
+// tx + 16 b) of the right-hand side; row j is published through LDS (double
+// buffered, one barrier per row).
+__global__ void __launch_bounds__(256) diag_finish_kernel(int n, double* __restrict__ L,
+                                                           const double* __restrict__ dfac,
+                                                           double* __restrict__ dinv) {
     __shared__ double Lb[NBK][NBK + 1];
-    __shared__ double Wb[NBK][NBK + 1];
-    __shared__ double rd[NBK];
+    __shared__ double wrow[2][NBK];
     const int B = blockIdx.x, kb = B * NBK, nb = min(NBK, n - kb);
     const double* in = dfac + (size_t)B * NBK * NBK;
-    const int c = threadIdx.x;
-    for (int i = 0; i < NBK; ++i) Lb[i][c] = (i < nb && c <= i) ? in[i * NBK + c] : 0.0;
+    for (int t = threadIdx.x; t < NBK * NBK; t += blockDim.x) {
+        const int i = t >> 6, c = t & 63;
+        Lb[i][c] = (i < nb && c <= i && c < nb) ? in[i * NBK + c] : (i == c ? 1.0 : 0.0);
+    }
     __syncthreads();
-    if (c < nb)
-        for (int i = 0; i < nb; ++i)
-            L[(size_t)(kb + i) * n + kb + c] = c <= i ? Lb[i][c] : Lb[c][i];
-    rd[c] = c < nb ? 1.0 / Lb[c][c] : 0.0;
-    __syncthreads();
-    for (int i = 0; i < NBK; ++i) {
-        double w = 0.0;
-        if (c < nb && i < nb && i >= c) {
-            if (i == c) {
-                w = rd[c];
-            } else {
-                double s = 0.0;
-                for (int j = c; j < i; ++j) s += Lb[i][j] * Wb[j][c];
-                w = -s * rd[i];
+    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+        const int i = t / nb, c = t % nb;
+        L[(size_t)(kb + i) * n + kb + c] = c <= i ? Lb[i][c] : Lb[c][i];
+    }
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double w[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) w[a][b] = (ty + 16 * a == tx + 16 * b) ? 1.0 : 0.0;
+#pragma unroll
+    for (int aj = 0; aj < 4; ++aj) {
+#pragma unroll 1
+        for (int jj = 0; jj < 16; ++jj) {
+            const int j = 16 * aj + jj;
+            const int buf = j & 1;
+            const double rd = 1.0 / Lb[j][j];
+            if (ty == jj) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    w[aj][b] *= rd;
+                    wrow[buf][tx + 16 * b] = w[aj][b];
+                }
             }
+            __syncthreads();
+            double wc[4], li[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) wc[b] = wrow[buf][tx + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) li[a] = ty + 16 * a > j ? Lb[ty + 16 * a][j] : 0.0;
+#pragma unroll
+            for (int a = aj; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) w[a][b] -= li[a] * wc[b];
         }
-        Wb[i][c] = w;   // lane c reads back only its own column
     }
-    __syncthreads();
     double* out = dinv + (size_t)B * 2 * NBK * NBK;
-    for (int i = 0; i < NBK; ++i) {
-        out[i * NBK + c] = Wb[i][c];
-        out[NBK * NBK + i * NBK + c] = Wb[c][i];
-    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = ty + 16 * a, c = tx + 16 * b;
+            const double v = (i < nb && c < nb) ? w[a][b] : 0.0;
+            out[i * NBK + c] = v;
+            out[NBK * NBK + c * NBK + i] = v;
+        }
 }
 
 // Upper triangle of L := L^T for the strictly lower 64 x 64 tiles (I > J),
@@ -234,10 +255,10 @@ __global__ void __launch_bounds__(256) syrk_kernel(int n, double* __restrict__ L
     const int J = rem;
     const int i0 = t0 + I * NBK, j0 = t0 + J * NBK;
     const int ni = min(NBK, n - i0), nj = min(NBK, n - j0);
-    for (int t = threadIdx.x; t < NBK * nb; t += blockDim.x) {
-        const int i = t / nb, c = t % nb;
-        PI[i][c] = i < ni ? L[(size_t)(i0 + i) * n + kb + c] : 0.0;
-        PJ[i][c] = i < nj ? L[(size_t)(j0 + i) * n + kb + c] : 0.0;
+    for (int t = threadIdx.x; t < NBK * NBK; t += blockDim.x) {
+        const int i = t >> 6, c = t & 63;
+        PI[i][c] = (i < ni && c < nb) ? L[(size_t)(i0 + i) * n + kb + c] : 0.0;
+        PJ[i][c] = (i < nj && c < nb) ? L[(size_t)(j0 + i) * n + kb + c] : 0.0;
     }
     __syncthreads();
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;   // 16 x 16 threads, 4x4 each
@@ -271,108 +292,78 @@ __global__ void __launch_bounds__(256) syrk_kernel(int n, double* __restrict__ L
     }
 }
 
-// y[i] -= sum_(q < nb) M[i n + col0 + q] yb[q] for row_lo <= i < row_hi.
-// 8 lanes per row, 8 contiguous doubles per lane; each lane keeps 4 rows'
-// loads in flight before reducing (FULL: nb = 64, no column guard).
-template <bool FULL>
-__device__ __forceinline__ void update_rows(const double* __restrict__ M, int n, int row_lo,
-                                            int row_hi, int col0, int nb,
-                                            const double* __restrict__ yb, double* y) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
-    const int sub = lane >> 3, part = lane & 7;
-    double yq[8];
+// Row block of the left-looking triangular sweep: for the nb rows r0 + i,
+//   u_i = y[r0 + i] - sum_(c in [c_lo, c_hi)) M[(r0 + i) n + c] y[c],
+// then y[r0 + i] = sum_k W[i][k] u_k (W: 64 x 64 row-major). y lives in LDS.
+// 16 threads per row (1024 threads: 64 rows); each thread issues 16 loads of
+// its stride-16 slice of the row before using them, so a row block costs a
+// few memory round trips; then one 64 x 64 mat-vec. The y[c] read are final
+// (other blocks), the writes touch only this block.
+__device__ __forceinline__ void trsv_block(const double* __restrict__ M, int n, int r0, int nb,
+                                           int c_lo, int c_hi, const double* __restrict__ W,
+                                           double* ys, double* ub) {
+    const int i = threadIdx.x >> 4, pt = threadIdx.x & 15;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < nb) {
+        const double* Mi = M + (size_t)(r0 + i) * n;
+        int c = c_lo + pt;
+        for (; c + 240 < c_hi; c += 256) {
+            double v[16];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) yq[q] = (FULL || part * 8 + q < nb) ? yb[part * 8 + q] : 0.0;
-    const int stride = nwv * 8;
-    for (int base = row_lo + wv * 8 + sub; base < row_hi; base += 4 * stride) {
-        double s[4];
+            for (int q = 0; q < 16; ++q) v[q] = Mi[c + 16 * q];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = base + u * stride;
-            s[u] = 0.0;
-            if (i < row_hi) {
-                const double* Mi = M + (size_t)i * n + col0 + part * 8;
-                if (FULL) {
-                    double v[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) v[q] = Mi[q];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) s[u] += v[q] * yq[q];
-                } else {
-                    for (int q = 0; q < 8 && part * 8 + q < nb; ++q) s[u] += Mi[q] * yq[q];
-                }
-            }
+            for (int q = 0; q < 16; ++q) acc[q & 3] += v[q] * ys[c + 16 * q];
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            double v = s[u];
-            v += __shfl_xor(v, 1, 64);
-            v += __shfl_xor(v, 2, 64);
-            v += __shfl_xor(v, 4, 64);
-            const int i = base + u * stride;
-            if (part == 0 && i < row_hi) y[i] -= v;
-        }
+        for (; c < c_hi; c += 16) acc[0] += Mi[c] * ys[c];
     }
-}
-
-// y_B := W y_B for the 64 x 64 block W (row-major): 16 threads per row, 4
-// columns each.
-__device__ __forceinline__ void block_matvec(const double* __restrict__ W, int r0, int nb,
-                                             double* y, double* yb) {
-    const int i = threadIdx.x >> 4, part = threadIdx.x & 15;
-    double s = 0.0;
-    if (i < NBK) {
-        const double* Wi = W + i * NBK + part * 4;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = part * 4 + q;
-            const double yc = c < nb ? y[r0 + c] : 0.0;
-            s += Wi[q] * yc;
-        }
-    }
+    double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     s += __shfl_xor(s, 1, 64);
     s += __shfl_xor(s, 2, 64);
     s += __shfl_xor(s, 4, 64);
     s += __shfl_xor(s, 8, 64);
-    __syncthreads();   // every read of y_B precedes the writes
-    if (part == 0 && i < nb) {
-        y[r0 + i] = s;
-        yb[i] = s;
-    }
+    if (pt == 0) ub[i] = i < nb ? ys[r0 + i] - s : 0.0;
+    __syncthreads();
+    double t = 0.0;
+    const double* Wi = W + i * NBK + pt * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t += Wi[q] * ub[pt * 4 + q];
+    t += __shfl_xor(t, 1, 64);
+    t += __shfl_xor(t, 2, 64);
+    t += __shfl_xor(t, 4, 64);
+    t += __shfl_xor(t, 8, 64);
+    if (pt == 0 && i < nb) ys[r0 + i] = t;
     __syncthreads();
 }
 
 // Solve (D G D) z = D b with the factor L (lower part; the upper part holds
-// L^T), then coef (+)= D z. One workgroup of 1024 threads, 64-row blocks:
-// forward, y_B = W_B y_B then the rows below are updated; backward,
-// z_B = W_B^T y_B then the rows above are updated from the rows of L^T.
+// L^T), then coef (+)= D z. One workgroup of 1024 threads, left-looking over
+// 64-row blocks: forward y_B = W_B (D b_B - L_(B, <B) y_<B), backward
+// z_B = W_B^T (y_B - (L^T)_(B, >B) z_>B), both reading rows of the stored
+// triangle. W_B, W_B^T: inverses of the diagonal blocks (dinv). The work
+// vector (n doubles) is held in dynamic LDS.
 __global__ void __launch_bounds__(1024) trsv_kernel(int n, const double* __restrict__ L,
                                                      const double* __restrict__ dinv,
                                                      const double* __restrict__ dsc,
-                                                     const double* b, double* y,
+                                                     const double* __restrict__ b,
                                                      double* __restrict__ coef, int accumulate,
                                                      const int* __restrict__ flag) {
-    __shared__ double yb[NBK];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = dsc[i] * b[i];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* ub = reinterpret_cast<double*>(smem_raw);
+    double* ys = ub + NBK;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) ys[i] = dsc[i] * b[i];
     __syncthreads();
     const int nblk = (n + NBK - 1) / NBK;
     for (int B = 0; B < nblk; ++B) {
         const int r0 = B * NBK, nb = min(NBK, n - r0);
-        block_matvec(dinv + (size_t)B * 2 * NBK * NBK, r0, nb, y, yb);
-        if (nb == NBK) update_rows<true>(L, n, r0 + nb, n, r0, nb, yb, y);
-        else update_rows<false>(L, n, r0 + nb, n, r0, nb, yb, y);
-        __syncthreads();
+        trsv_block(L, n, r0, nb, 0, r0, dinv + (size_t)B * 2 * NBK * NBK, ys, ub);
     }
     for (int B = nblk - 1; B >= 0; --B) {
         const int r0 = B * NBK, nb = min(NBK, n - r0);
-        block_matvec(dinv + (size_t)B * 2 * NBK * NBK + NBK * NBK, r0, nb, y, yb);
-        if (nb == NBK) update_rows<true>(L, n, 0, r0, r0, nb, yb, y);
-        else update_rows<false>(L, n, 0, r0, r0, nb, yb, y);
-        __syncthreads();
+        trsv_block(L, n, r0, nb, r0 + nb, n, dinv + (size_t)B * 2 * NBK * NBK + NBK * NBK, ys, ub);
     }
     const bool bad = *flag != 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double z = bad ? __builtin_nan("") : dsc[i] * y[i];
+        const double z = bad ? __builtin_nan("") : dsc[i] * ys[i];
         coef[i] = accumulate ? coef[i] + z : z;
     }
 }
@@ -403,16 +394,22 @@ hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* fl
         }
     }
     const int T = (n + NBK - 1) / NBK;
-    hipLaunchKernelGGL(diag_finish_kernel, dim3(T), dim3(64), 0, st, n, L, dfac, dinv);
+    hipLaunchKernelGGL(diag_finish_kernel, dim3(T), dim3(256), 0, st, n, L, dfac, dinv);
     if (T > 1) hipLaunchKernelGGL(mirror_kernel, dim3(T * (T - 1) / 2), dim3(256), 0, st, n, L);
     return hipGetLastError();
 }
 
 hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const double* dsc,
-                             double* rhs, double* coef, int accumulate, const int* flag,
+                             const double* rhs, double* coef, int accumulate, const int* flag,
                              hipStream_t st) {
-    // rhs holds b on entry and is used as the work vector y
-    hipLaunchKernelGGL(trsv_kernel, dim3(1), dim3(1024), 0, st, n, L, dinv, dsc, rhs, rhs, coef,
+    const size_t lds = (size_t)(n + NBK) * sizeof(double);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(trsv_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(trsv_kernel, dim3(1), dim3(1024), lds, st, n, L, dinv, dsc, rhs, coef,
                        accumulate, flag);
     return hipGetLastError();
 }

@@ -24,17 +24,18 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
                                                       const Tin* __restrict__ img1,
                                                       const double* __restrict__ ped,
                                                       cx<T>* __restrict__ Z,
-                                                      const cx<T>* __restrict__ tw) {
+                                                      const cx<T>* __restrict__ twt) {
     cx<T>* lds = lds_base<T>();
     const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
     const int row = blockIdx.x * lp.lpw + line;
     const bool act = row < g.n0;
     const int n1 = g.n1;
-    cx<T>* buf = lds + line * lp.n;
+    cx<T>* buf = lds + line * line_lds_elems(n1);
     const int npk = (src.n + 1) / 2;
     for (int pk = 0; pk < npk; ++pk) {
         const int ia = 2 * pk, ib = 2 * pk + 1;
         const bool hasb = ib < src.n;
+        cx<T> v[kElemsPerThread];
         if (act) {
             const Tin* pa = (src.img[ia] ? img1 : img0) + (size_t)row * n1;
             const Tin* pb = (hasb && src.img[ib] ? img1 : img0) + (size_t)row * n1;
@@ -47,16 +48,23 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
                 const T c = coord<T>(x1, n1);
                 const T va = ipow(c, ea) * T((double)pa[x1] - qa);
                 const T vb = hasb ? ipow(c, eb) * T((double)pb[x1] - qb) : T(0);
-                buf[x1] = mk(va, vb);
+                v[e] = mk(va, vb);
             }
+        } else {
+#pragma unroll
+            for (int e = 0; e < kElemsPerThread; ++e) v[e] = mk(T(0), T(0));
         }
+        line_fft_regs<-1, T>(v, buf, lp, lt, twt);
+        // separate the two real rows: needs X(m) and X(N1 - m) together
         __syncthreads();
-        line_fft<-1, T>(buf, lp, lt, tw);
+#pragma unroll
+        for (int e = 0; e < kElemsPerThread; ++e) buf[lpad(lt + e * lp.tl)] = v[e];
+        __syncthreads();
         if (act) {
             cx<T>* za = Z + ((size_t)src.out[ia] * g.n0 + row) * g.hp;
             cx<T>* zb = Z + ((size_t)(hasb ? src.out[ib] : 0) * g.n0 + row) * g.hp;
             for (int m = lt; m < g.h; m += lp.tl) {
-                const cx<T> a = buf[m], b = buf[m == 0 ? 0 : n1 - m];
+                const cx<T> a = buf[lpad(m)], b = buf[lpad(m == 0 ? 0 : n1 - m)];
                 za[m] = mk((a.re + b.re) * T(0.5), (a.im - b.im) * T(0.5));
                 if (hasb) zb[m] = mk((a.im + b.im) * T(0.5), (b.re - a.re) * T(0.5));
             }
@@ -69,7 +77,7 @@ template <typename T>
 __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJobs jobs,
                                                       const cx<T>* __restrict__ Z,
                                                       cx<T>* __restrict__ X,
-                                                      const cx<T>* __restrict__ tw) {
+                                                      const cx<T>* __restrict__ twt) {
     cx<T>* lds = lds_base<T>();
     const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
     // Block -> (column block, job): workgroups are dealt to the 8 XCDs round
@@ -84,7 +92,7 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
     const bool act = m < g.h;
     const int n0 = g.n0;
     const int a = jobs.arr[job];
-    cx<T>* buf = lds + line * lp.n;
+    cx<T>* buf = lds + line * line_lds_elems(lp.n);
     cx<T> z[kElemsPerThread];
     if (act) {
         const cx<T>* zc = Z + (size_t)a * n0 * g.hp + m;
@@ -93,24 +101,18 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
     }
     const int nw = jobs.nw[job];
     for (int i = 0; i < nw; ++i) {
-        if (act) {
+        cx<T> v[kElemsPerThread];
 #pragma unroll
-            for (int e = 0; e < kElemsPerThread; ++e) {
-                const int x0 = lt + e * lp.tl;
-                buf[x0] = cscale(z[e], ipow(coord<T>(x0, n0), i));
-            }
+        for (int e = 0; e < kElemsPerThread; ++e) {
+            const int x0 = lt + e * lp.tl;
+            v[e] = act ? cscale(z[e], ipow(coord<T>(x0, n0), i)) : mk(T(0), T(0));
         }
-        __syncthreads();
-        line_fft<-1, T>(buf, lp, lt, tw);
+        line_fft_regs<-1, T>(v, buf, lp, lt, twt);
         if (act) {
             cx<T>* xo = X + ((size_t)jobs.spec[job][i] * g.h + m) * n0;
 #pragma unroll
-            for (int e = 0; e < kElemsPerThread; ++e) {
-                const int l = lt + e * lp.tl;
-                xo[l] = buf[l];
-            }
+            for (int e = 0; e < kElemsPerThread; ++e) xo[lt + e * lp.tl] = v[e];
         }
-        __syncthreads();
     }
 }
 
@@ -123,14 +125,15 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
                                                       const cx<T>* __restrict__ Dt,
                                                       Tout* __restrict__ d,
                                                       const double* __restrict__ sky,
-                                                      const cx<T>* __restrict__ tw) {
+                                                      const cx<T>* __restrict__ twt) {
     cx<T>* lds = lds_base<T>();
     const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
     const int pr = blockIdx.x * lp.lpw + line;
     const int xa = 2 * pr, xb = 2 * pr + 1;
     const bool act = xb < g.n0;
     const int n1 = g.n1;
-    cx<T>* buf = lds + line * lp.n;
+    cx<T>* buf = lds + line * line_lds_elems(lp.n);
+    cx<T> v[kElemsPerThread];
     if (act) {
         const cx<T>* A = Dt + (size_t)xa * g.hp;
         const cx<T>* B = Dt + (size_t)xb * g.hp;
@@ -146,11 +149,13 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
                 a = cconj(A[n1 - m]);
                 b = cconj(B[n1 - m]);
             }
-            buf[m] = mk(a.re - b.im, a.im + b.re);
+            v[e] = mk(a.re - b.im, a.im + b.re);
         }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kElemsPerThread; ++e) v[e] = mk(T(0), T(0));
     }
-    __syncthreads();
-    line_fft<1, T>(buf, lp, lt, tw);
+    line_fft_regs<1, T>(v, buf, lp, lt, twt);
     if (act) {
         const double inv = 1.0 / (double)n1;
         const int n0 = g.n0, w0 = g.w0, R = max(g.dk, g.db);
@@ -175,9 +180,8 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
             }
             if (ra) ba = ra[x1];
             if (rb) bb = rb[x1];
-            const cx<T> v = buf[x1];
-            d[(size_t)xa * n1 + x1] = Tout((double)v.re * inv - ba);
-            d[(size_t)xb * n1 + x1] = Tout((double)v.im * inv - bb);
+            d[(size_t)xa * n1 + x1] = Tout((double)v[e].re * inv - ba);
+            d[(size_t)xb * n1 + x1] = Tout((double)v[e].im * inv - bb);
         }
     }
 }
@@ -186,18 +190,20 @@ template <typename T, int S>
 __global__ void __launch_bounds__(512) fft_lines_kernel(LinePlan lp, int nlines,
                                                          const cx<T>* __restrict__ in,
                                                          cx<T>* __restrict__ out,
-                                                         const cx<T>* __restrict__ tw) {
+                                                         const cx<T>* __restrict__ twt) {
     cx<T>* lds = lds_base<T>();
     const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
     const int ln = blockIdx.x * lp.lpw + line;
     const bool act = ln < nlines;
-    cx<T>* buf = lds + line * lp.n;
+    cx<T>* buf = lds + line * line_lds_elems(lp.n);
+    cx<T> v[kElemsPerThread];
+#pragma unroll
+    for (int e = 0; e < kElemsPerThread; ++e)
+        v[e] = act ? in[(size_t)ln * lp.n + lt + e * lp.tl] : mk(T(0), T(0));
+    line_fft_regs<S, T>(v, buf, lp, lt, twt);
     if (act)
-        for (int e = 0; e < kElemsPerThread; ++e) buf[lt + e * lp.tl] = in[(size_t)ln * lp.n + lt + e * lp.tl];
-    __syncthreads();
-    line_fft<S, T>(buf, lp, lt, tw);
-    if (act)
-        for (int e = 0; e < kElemsPerThread; ++e) out[(size_t)ln * lp.n + lt + e * lp.tl] = buf[lt + e * lp.tl];
+#pragma unroll
+        for (int e = 0; e < kElemsPerThread; ++e) out[(size_t)ln * lp.n + lt + e * lp.tl] = v[e];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -212,57 +218,57 @@ static hipError_t set_lds(K kern, size_t bytes) {
 
 template <typename T, typename Tin>
 hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& src, const Tin* img0,
-                         const Tin* img1, const double* ped, cx<T>* Z, const cx<T>* tw,
+                         const Tin* img1, const double* ped, cx<T>* Z, const cx<T>* twt,
                          hipStream_t st) {
-    const size_t lds = (size_t)lp.lpw * lp.n * sizeof(cx<T>);
+    const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     auto k = rowfwd_kernel<T, Tin>;
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     dim3 grid((g.n0 + lp.lpw - 1) / lp.lpw);
-    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, src, img0, img1, ped, Z, tw);
+    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, src, img0, img1, ped, Z, twt);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs, const cx<T>* Z,
-                         cx<T>* X, const cx<T>* tw, hipStream_t st) {
-    const size_t lds = (size_t)lp.lpw * lp.n * sizeof(cx<T>);
+                         cx<T>* X, const cx<T>* twt, hipStream_t st) {
+    const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     auto k = colfwd_kernel<T>;
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
     dim3 grid((ncb + 127) / 128 * 128 * jobs.narr);
-    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, jobs, Z, X, tw);
+    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, jobs, Z, X, twt);
     return hipGetLastError();
 }
 
 template <typename T, typename Tout>
 hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, Tout* d,
-                         const double* sky, const cx<T>* tw, hipStream_t st) {
-    const size_t lds = (size_t)lp.lpw * lp.n * sizeof(cx<T>);
+                         const double* sky, const cx<T>* twt, hipStream_t st) {
+    const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     auto k = rowinv_kernel<T, Tout>;
     hipError_t e = set_lds(k, lds);
     if (e != hipSuccess) return e;
     dim3 grid((g.n0 / 2 + lp.lpw - 1) / lp.lpw);
-    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, Dt, d, sky, tw);
+    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, Dt, d, sky, twt);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_fft_lines(const LinePlan& lp, int nlines, int sign, const cx<T>* in, cx<T>* out,
-                            const cx<T>* tw, hipStream_t st) {
-    const size_t lds = (size_t)lp.lpw * lp.n * sizeof(cx<T>);
+                            const cx<T>* twt, hipStream_t st) {
+    const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     dim3 grid((nlines + lp.lpw - 1) / lp.lpw);
     if (sign < 0) {
         auto k = fft_lines_kernel<T, -1>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, lp, nlines, in, out, tw);
+        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, lp, nlines, in, out, twt);
     } else {
         auto k = fft_lines_kernel<T, 1>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, lp, nlines, in, out, tw);
+        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, lp, nlines, in, out, twt);
     }
     return hipGetLastError();
 }

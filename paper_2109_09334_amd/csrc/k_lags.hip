@@ -14,6 +14,7 @@
 #include "fft_engine.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
 #include <cstdlib>
 
 namespace sfft {
@@ -38,7 +39,7 @@ template <typename T>
 __global__ void __launch_bounds__(512) lagcol_kernel(Geom g, LinePlan lp, int p0, int np, int sslot,
                                                       const cx<T>* __restrict__ X,
                                                       cx<T>* __restrict__ Cl,
-                                                      const cx<T>* __restrict__ tw) {
+                                                      const cx<T>* __restrict__ twt) {
     cx<T>* lds = lds_base_l<T>();
     const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
     // Block -> (column block, product): the products of one column block run
@@ -55,22 +56,28 @@ __global__ void __launch_bounds__(512) lagcol_kernel(Geom g, LinePlan lp, int p0
     if (p < g.npair) decode_pair(g.P, p, kb, k);
     else { kb = p - g.npair; k = sslot; }
     const int K = p < g.npair ? 2 * g.w0 : g.w0;
-    cx<T>* buf = lds + line * lp.n;
+    cx<T>* buf = lds + line * line_lds_elems(lp.n);
+    cx<T> v[kElemsPerThread];
     if (act) {
         const cx<T>* A = X + ((size_t)kb * g.h + m) * n0;
         const cx<T>* B = X + ((size_t)k * g.h + m) * n0;
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) {
             const int l = lt + e * lp.tl;
-            buf[l] = cmulc(A[l], B[l]);
+            v[e] = cmulc(A[l], B[l]);
         }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kElemsPerThread; ++e) v[e] = mk(T(0), T(0));
     }
-    __syncthreads();
-    line_fft<1, T>(buf, lp, lt, tw);
+    line_fft_regs<1, T>(v, buf, lp, lt, twt);
     if (act) {
-        for (int t = lt; t <= 2 * K; t += lp.tl) {
-            const int d0 = t - K;
-            Cl[((size_t)p * g.D0 + d0 + 2 * g.w0) * g.hp + m] = buf[imod(d0, n0)];
+#pragma unroll
+        for (int e = 0; e < kElemsPerThread; ++e) {
+            const int l = lt + e * lp.tl;   // lag d0 = l or l - N0
+            const int d0 = l <= K ? l : l - n0;
+            if (d0 >= -K && d0 <= K)
+                Cl[((size_t)p * g.D0 + d0 + 2 * g.w0) * g.hp + m] = v[e];
         }
     }
 }
@@ -114,13 +121,17 @@ __device__ __forceinline__ void wave_transpose_sum16(cx<T>* v, int lane) {
 
 template <typename T>
 __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, int ir_only,
-                                                           int sslot, const cx<T>* __restrict__ X,
+                                                           int sslot, int pchunk,
+                                                           const cx<T>* __restrict__ X,
                                                            cx<T>* __restrict__ Cl,
                                                            const cx<T>* __restrict__ tw) {
-    __shared__ cx<T> red[8][16];
+    // red[product in chunk][lag block][wave of the workgroup][16]: wave sums
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* red = reinterpret_cast<cx<T>*>(smem_raw);
     const int tl = lp.tl;                       // M: threads per line, multiple of 64
     const int line = threadIdx.x / tl, j = threadIdx.x - line * tl;
-    const int lane = threadIdx.x & 63, wl = j >> 6, nwl = tl >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    const int nwl = tl >> 6;                    // waves per line
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
     const int jx = slot / g.P;
     const int kb = slot - jx * g.P;
@@ -128,6 +139,7 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
     const int m = cb * lp.lpw + line;
     const bool act = m < g.h;
     const int n0 = g.n0;
+    const int KO = 2 * g.w0, nblk = (2 * KO + 16) / 16;   // lag blocks of Omega (Theta uses fewer)
     cx<T> a[16];
     if (act) {
         const cx<T>* A = X + ((size_t)kb * g.h + m) * n0 + j;
@@ -135,37 +147,61 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
         for (int q = 0; q < 16; ++q) a[q] = A[(size_t)q * tl];
     }
     const int kfirst = ir_only ? g.P : kb;
-    for (int kk = kfirst; kk <= g.P; ++kk) {
-        const bool theta = kk == g.P;
-        const int k = theta ? sslot : kk;
-        const int p = theta ? g.npair + kb : kb * g.P - kb * (kb - 1) / 2 + (kk - kb);
-        const int K = theta ? g.w0 : 2 * g.w0;
-        cx<T> v[16];
-        if (act) {
-            const cx<T>* B = X + ((size_t)k * g.h + m) * n0 + j;
+    for (int k0 = kfirst; k0 <= g.P; k0 += pchunk) {
+        const int k1 = min(g.P + 1, k0 + pchunk);
+        for (int kk = k0; kk < k1; ++kk) {
+            const bool theta = kk == g.P;
+            const int k = theta ? sslot : kk;
+            const int K = theta ? g.w0 : KO;
+            cx<T> v[16];
+            if (act) {
+                const cx<T>* B = X + ((size_t)k * g.h + m) * n0 + j;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = cmulc(a[q], B[(size_t)q * tl]);
-            Dft<16, 1, T>::run(v);
-        }
-        for (int tb = -K; tb <= K; tb += 16) {
-            cx<T> s[16];
+                for (int q = 0; q < 16; ++q) v[q] = cmulc(a[q], B[(size_t)q * tl]);
+                Dft<16, 1, T>::run(v);
+            } else {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int t = tb + ((r - tb) & 15);
-                const cx<T> w = tw[imod(j * t, n0)];     // e^(-2 pi i j t / N0)
-                s[r] = act ? cmul(v[r], cconj(w)) : mk(T(0), T(0));
+                for (int q = 0; q < 16; ++q) v[q] = mk(T(0), T(0));
             }
-            wave_transpose_sum16(s, lane);
-            if ((lane & 3) == 0) red[line * nwl + wl][(lane >> 2) & 15] = s[0];
-            __syncthreads();
-            if (act && j < 16) {
-                cx<T> tot = red[line * nwl][j];
-                for (int w = 1; w < nwl; ++w) tot = tot + red[line * nwl + w][j];
-                const int t = tb + ((j - tb) & 15);
-                if (t <= K) Cl[((size_t)p * g.D0 + t + 2 * g.w0) * g.hp + m] = tot;
+            for (int blk = 0; 16 * blk <= 2 * K; ++blk) {
+                const int tb = -K + 16 * blk;
+                const int mres = tb & 15;
+                cx<T> s[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    // slot r carries lag t = tb + ((r - tb) mod 16)
+                    // (|t| <= 4 w0 + 15 and j < N0/16 with 4 w0 < N0: |j t| < 3 N0)
+                    const int t = tb - mres + r + (r < mres ? 16 : 0);
+                    int idx = j * t;
+#pragma unroll
+                    for (int c3 = 0; c3 < 3; ++c3) idx += idx < 0 ? n0 : 0;
+#pragma unroll
+                    for (int c3 = 0; c3 < 3; ++c3) idx -= idx >= n0 ? n0 : 0;
+                    s[r] = cmul(v[r], cconj(tw[idx]));   // e^(+2 pi i j t / N0)
+                }
+                wave_transpose_sum16(s, lane);
+                if ((lane & 3) == 0)
+                    red[(((size_t)(kk - k0) * nblk + blk) * nwv + wv) * 16 + ((lane >> 2) & 15)] = s[0];
             }
-            __syncthreads();
         }
+        __syncthreads();
+        // line sums: one output (product, block, slot) per thread of the line
+        const int nout = (k1 - k0) * nblk * 16;
+        for (int o = j; o < nout; o += tl) {
+            const int r = o & 15, blk = (o >> 4) % nblk, ip = (o >> 4) / nblk;
+            const int kk = k0 + ip;
+            const bool theta = kk == g.P;
+            const int K = theta ? g.w0 : KO;
+            const int tb = -K + 16 * blk;
+            const int t = tb + ((r - tb) & 15);
+            if (!act || 16 * blk > 2 * K || t > K) continue;
+            cx<T> tot = red[(((size_t)ip * nblk + blk) * nwv + line * nwl) * 16 + r];
+            for (int w = 1; w < nwl; ++w)
+                tot = tot + red[(((size_t)ip * nblk + blk) * nwv + line * nwl + w) * 16 + r];
+            const int p = theta ? g.npair + kb : kb * g.P - kb * (kb - 1) / 2 + (kk - kb);
+            Cl[((size_t)p * g.D0 + t + 2 * g.w0) * g.hp + m] = tot;
+        }
+        __syncthreads();
     }
 }
 
@@ -248,18 +284,23 @@ __global__ void __launch_bounds__(256) lagrow_kernel(Geom g, int p0, const cx<T>
 
 template <typename T>
 hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int sslot,
-                         const cx<T>* X, cx<T>* Cl, const cx<T>* tw, hipStream_t st) {
+                         const cx<T>* X, cx<T>* Cl, const cx<T>* tw, const cx<T>* twt,
+                         hipStream_t st) {
     if (p1 <= p0) return hipSuccess;
     static const bool force_full = getenv("SFFT_LAGCOL_FULL") != nullptr;
     if (!force_full && lp.tl % 64 == 0 && lp.tl * lp.lpw <= 512 &&
         ((p0 == 0 && p1 == g.nprod) || (p0 == g.npair && p1 == g.nprod))) {
         const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
+        const int nwv = lp.tl * lp.lpw / 64;
+        const int nblk = (4 * g.w0 + 16) / 16;
+        const size_t per = (size_t)nblk * nwv * 16 * sizeof(cx<T>);
+        const int pchunk = (int)std::max<size_t>(1, std::min<size_t>(g.P + 1, 32768 / per));
         dim3 grid((ncb + 7) / 8 * 8 * g.P);
-        hipLaunchKernelGGL(lagcol_tail_kernel<T>, grid, dim3(lp.tl * lp.lpw), 0, st, g, lp,
-                           p0 == 0 ? 0 : 1, sslot, X, Cl, tw);
+        hipLaunchKernelGGL(lagcol_tail_kernel<T>, grid, dim3(lp.tl * lp.lpw), pchunk * per, st, g,
+                           lp, p0 == 0 ? 0 : 1, sslot, pchunk, X, Cl, tw);
         return hipGetLastError();
     }
-    const size_t lds = (size_t)lp.lpw * lp.n * sizeof(cx<T>);
+    const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     auto k = lagcol_kernel<T>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
@@ -268,7 +309,7 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
     }
     const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
     dim3 grid((ncb + 7) / 8 * 8 * (p1 - p0));
-    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, p0, p1 - p0, sslot, X, Cl, tw);
+    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, p0, p1 - p0, sslot, X, Cl, twt);
     return hipGetLastError();
 }
 
@@ -282,10 +323,11 @@ hipError_t launch_lagrow(const Geom& g, int p0, int p1, const cx<T>* Cl, const d
 }
 
 template hipError_t launch_lagcol<float>(const Geom&, const LinePlan&, int, int, int,
-                                         const cx<float>*, cx<float>*, const cx<float>*, hipStream_t);
+                                         const cx<float>*, cx<float>*, const cx<float>*,
+                                         const cx<float>*, hipStream_t);
 template hipError_t launch_lagcol<double>(const Geom&, const LinePlan&, int, int, int,
                                           const cx<double>*, cx<double>*, const cx<double>*,
-                                          hipStream_t);
+                                          const cx<double>*, hipStream_t);
 template hipError_t launch_lagrow<float>(const Geom&, int, int, const cx<float>*, const double*,
                                          double*, double*, hipStream_t);
 template hipError_t launch_lagrow<double>(const Geom&, int, int, const cx<double>*, const double*,

@@ -30,24 +30,26 @@ struct ColJobs {
 
 template <typename T, typename Tin>
 hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& src, const Tin* img0,
-                         const Tin* img1, const double* ped, cx<T>* Z, const cx<T>* tw,
+                         const Tin* img1, const double* ped, cx<T>* Z, const cx<T>* twt,
                          hipStream_t st);
 template <typename T>
 hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs, const cx<T>* Z,
-                         cx<T>* X, const cx<T>* tw, hipStream_t st);
+                         cx<T>* X, const cx<T>* twt, hipStream_t st);
 template <typename T, typename Tout>
 hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, Tout* d,
-                         const double* sky, const cx<T>* tw, hipStream_t st);
+                         const double* sky, const cx<T>* twt, hipStream_t st);
 template <typename T>
 hipError_t launch_fft_lines(const LinePlan& lp, int nlines, int sign, const cx<T>* in, cx<T>* out,
-                            const cx<T>* tw, hipStream_t st);
+                            const cx<T>* twt, hipStream_t st);
 
 // Products conj(X[kb]) X[k] for products p in [p0, p1): pairs kb <= k of the
 // kernel spectra (p < npair) then (kb, S-slot) with the S spectrum at
 // index sslot. Pruned inverse along axis 0 kept for |d0| <= lag range.
 template <typename T>
+// tw: full twiddle table W_N0^t; twt: pass tables of the line plan.
 hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int sslot,
-                         const cx<T>* X, cx<T>* Cl, const cx<T>* tw, hipStream_t st);
+                         const cx<T>* X, cx<T>* Cl, const cx<T>* tw, const cx<T>* twt,
+                         hipStream_t st);
 template <typename T>
 hipError_t launch_lagrow(const Geom& g, int p0, int p1, const cx<T>* Cl, const double* twp,
                          double* omega, double* theta, hipStream_t st);
@@ -85,8 +87,9 @@ hipError_t launch_jacobi(int n, const double* G, const double* h, double* L, dou
 // with the factor in its lower and its transpose in its upper triangle.
 hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* flag,
                            hipStream_t st);
+// coef (+)= solution of G c = rhs (rhs is read only).
 hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const double* dsc,
-                             double* rhs, double* coef, int accumulate, const int* flag,
+                             const double* rhs, double* coef, int accumulate, const int* flag,
                              hipStream_t st);
 hipError_t launch_clear_flag(int* flag, hipStream_t st);
 

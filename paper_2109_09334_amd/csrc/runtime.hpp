@@ -94,6 +94,7 @@ inline size_t carve(Workspace& w, const Geom& g, size_t cxb, size_t reb, char* b
 // Twiddle tables of one line length.
 struct Twiddles {
     void* tw = nullptr;       // n complex of the compute type: e^(-2 pi i t / n)
+    void* twt = nullptr;      // pass tables of the line plan (compute type)
     double* twp = nullptr;    // 2n doubles: cos, sin of +2 pi t / n
 };
 
