@@ -11,6 +11,8 @@
 // the line holds its transform in natural order. S = -1 is the forward
 // (e^-) transform, S = +1 the unnormalised inverse.
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace sfft {
@@ -217,6 +219,90 @@ __device__ __forceinline__ void line_fft_regs(cx<T>* v, cx<T>* buf, const LinePl
     } else {
 #pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = buf[lpad(lt + e * tl)];
+    }
+}
+
+// ---- compile-time plans for the common line lengths ----------------------
+// The same passes as line_fft_regs with the radix sequence (and so every ns)
+// known at compile time: no radix switch (whose union of code paths holds
+// ~60 more VGPRs) and no runtime modulo. The sequences equal the runtime
+// plans' order, so the same pass twiddle tables serve both.
+template <int... R>
+struct RadixSeq {};
+struct DynPlan {};
+
+template <int... R>
+struct SeqProd;
+template <>
+struct SeqProd<> {
+    static constexpr int value = 1;
+};
+template <int R, int... Rest>
+struct SeqProd<R, Rest...> {
+    static constexpr int value = R * SeqProd<Rest...>::value;
+};
+
+// Passes after the first, starting with radix R at stride NS; twoff is the
+// offset of this pass's twiddle table.
+template <int S, typename T, int N, int NS, int R, int... Rest>
+__device__ __forceinline__ void passes_static(cx<T>* v, cx<T>* buf, int lt,
+                                              const cx<T>* __restrict__ twt, int twoff) {
+    constexpr int TL = N / kElemsPerThread;
+    if constexpr (sizeof...(Rest) == 0 && R == 16) {
+        cx<T> w[16];
+        load_twiddles<16, S>(w, twt + twoff + (size_t)lt * 16);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = buf[lpad(lt + r * TL)];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
+        Dft<16, S, T>::run(v);
+    } else {
+        pass_lds<R, S, T>(buf, N, NS, lt, TL, twt + twoff);
+        if constexpr (sizeof...(Rest) > 0) {
+            passes_static<S, T, N, NS * R, Rest...>(v, buf, lt, twt, twoff + NS * 16);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = buf[lpad(lt + e * TL)];
+        }
+    }
+}
+
+template <int S, typename T, int... Rs>
+__device__ __forceinline__ void line_fft_static(cx<T>* v, cx<T>* buf, int lt,
+                                                const cx<T>* __restrict__ twt, RadixSeq<16, Rs...>) {
+    Dft<16, S, T>::run(v);
+    if constexpr (sizeof...(Rs) > 0) {
+        constexpr int N = 16 * SeqProd<Rs...>::value;
+        __syncthreads();   // buf may still be read by a previous transform
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[lpad(16 * lt + r)] = v[r];
+        __syncthreads();
+        passes_static<S, T, N, 16, Rs...>(v, buf, lt, twt, 0);
+    }
+}
+
+// Line transform with the plan PL: RadixSeq<...> (compile time) or DynPlan
+// (lp at run time). Same contract as line_fft_regs.
+template <int S, typename T, typename PL>
+__device__ __forceinline__ void line_fft(cx<T>* v, cx<T>* buf, const LinePlan& lp, int lt,
+                                         const cx<T>* __restrict__ twt) {
+    if constexpr (std::is_same<PL, DynPlan>::value) {
+        line_fft_regs<S, T>(v, buf, lp, lt, twt);
+    } else {
+        line_fft_static<S, T>(v, buf, lt, twt, PL{});
+    }
+}
+
+// Calls f(PL{}) with the compile-time plan of length n, or DynPlan.
+template <typename F>
+inline hipError_t with_line_plan(int n, F&& f) {
+    switch (n) {
+        case 4096: return f(RadixSeq<16, 16, 16>{});
+        case 2048: return f(RadixSeq<16, 8, 16>{});
+        case 1024: return f(RadixSeq<16, 4, 16>{});
+        case 8192: return f(RadixSeq<16, 2, 16, 16>{});
+        case 6144: return f(RadixSeq<16, 8, 3, 16>{});
+        default: return f(DynPlan{});
     }
 }
 

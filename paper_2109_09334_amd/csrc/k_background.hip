@@ -25,7 +25,6 @@
 namespace sfft {
 
 constexpr int kMaxMom = 2 * kMaxDegree + 1;
-constexpr int kRowChunk = 64;
 
 template <int NV>
 __device__ __forceinline__ void block_sum_bg(double* v, double* red) {
@@ -48,38 +47,51 @@ __device__ __forceinline__ void block_sum_bg(double* v, double* red) {
     __syncthreads();
 }
 
-// One row per block: V[u0][ja][jb][d1 + K1], ja <= da, jb <= db, |d1| <= K1.
-template <typename Tin>
+// One wave per row (four rows per 256-thread block):
+// V[u0][ja][jb][d1 + K1], ja <= da, jb <= db, |d1| <= K1. The row moments
+// are wave sums (every lane ends with all of them); the wrapped-column
+// corrections read the row again (L1).
+template <typename Tin, int NE>
 __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, const Tin* __restrict__ img, int da,
                                                       int dbb, int K1, double* __restrict__ vrow) {
-    __shared__ double red[4 * kMaxMom];
-    const int x0 = blockIdx.x;
+    __shared__ double mom[4][kMaxMom];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int x0 = blockIdx.x * 4 + wv;
+    if (x0 >= g.n0) return;   // wave-level work only below
     const int n1 = g.n1;
-    const int ne = da + dbb + 1;
     const Tin* row = img + (size_t)x0 * n1;
-    double mo[kMaxMom];
+    // c1(x1) = (2 x1 - (N1 - 1)) / (N1 - 1) with the division as a product
+    const double rn = 1.0 / (double)(n1 - 1);
+    double mo[NE];
 #pragma unroll
-    for (int e = 0; e < kMaxMom; ++e) mo[e] = 0.0;
-    for (int x1 = threadIdx.x; x1 < n1; x1 += blockDim.x) {
-        const double c = coord<double>(x1, n1);
-        const double v = (double)row[x1];
-        double pw = 1.0;
+    for (int e = 0; e < NE; ++e) mo[e] = 0.0;
+    for (int x1 = lane; x1 < n1; x1 += 64) {
+        const double c = (double)(2 * x1 - (n1 - 1)) * rn;
+        double pw = (double)row[x1];
 #pragma unroll
-        for (int e = 0; e < kMaxMom; ++e) {
-            if (e < ne) mo[e] += v * pw;
+        for (int e = 0; e < NE; ++e) {
+            mo[e] += pw;
             pw *= c;
         }
     }
-    block_sum_bg<kMaxMom>(mo, red);   // red[0..kMaxMom) = row moments
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        double x = mo[e];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) mom[wv][e] = x;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const int na = da + 1, nb = dbb + 1, nd = 2 * K1 + 1;
     const double del = 2.0 / (double)(n1 - 1);
-    for (int idx = threadIdx.x; idx < na * nb * nd; idx += blockDim.x) {
+    for (int idx = lane; idx < na * nb * nd; idx += 64) {
         const int ja = idx / (nb * nd);
         const int jb = (idx / nd) % nb;
         const int d1 = idx % nd - K1;
         const double sh = del * (double)d1;
         double v = 0.0;
-        for (int r = 0; r <= jb; ++r) v += binom(jb, r) * ipow(sh, jb - r) * red[ja + r];
+        for (int r = 0; r <= jb; ++r) v += binom(jb, r) * ipow(sh, jb - r) * mom[wv][ja + r];
         const int lo = d1 > 0 ? n1 - d1 : 0, hi = d1 > 0 ? n1 : -d1;
         for (int x1 = lo; x1 < hi; ++x1) {
             const double c = coord<double>(x1, n1);
@@ -95,13 +107,13 @@ __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, const Tin* __restr
 //   Pi_{(ia,ja)(ib,jb)}(d0, d1) = sum_r C(ib,r) s^(ib-r) Mom_{ia+r}(ja, jb, d1)
 //                                 + wrapped-row correction,
 // with the axis-0 moments Mom_e(item) = sum_x0 c0(x0)^e V(x0, item) and
-// item = (ja, jb, d1). The moments are summed per chunk of kRowChunk rows,
+// item = (ja, jb, d1). The moments are summed per chunk of kPolyRowChunk rows,
 // then the chunks in a fixed order (no atomics: the result does not depend
 // on scheduling).
 __global__ void __launch_bounds__(256) polymom_kernel(Geom g, const double* __restrict__ vrow,
                                                        int nitem, int ne,
                                                        double* __restrict__ part) {
-    const int x0a = blockIdx.x * kRowChunk, x0b = min(g.n0, x0a + kRowChunk);
+    const int x0a = blockIdx.x * kPolyRowChunk, x0b = min(g.n0, x0a + kPolyRowChunk);
     for (int item = threadIdx.x; item < nitem; item += blockDim.x) {
         double m[kMaxMom];
 #pragma unroll
@@ -121,14 +133,18 @@ __global__ void __launch_bounds__(256) polymom_kernel(Geom g, const double* __re
     }
 }
 
+// mom[i] = sum over the row chunks (fixed order per lane, then a wave sum).
 __global__ void __launch_bounds__(256) momsum_kernel(int nchunk, int nval,
                                                       const double* __restrict__ part,
                                                       double* __restrict__ mom) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= nval) return;
     double s = 0.0;
-    for (int k = 0; k < nchunk; ++k) s += part[(size_t)k * nval + i];
-    mom[i] = s;
+    for (int k = lane; k < nchunk; k += 64) s += part[(size_t)k * nval + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) mom[i] = s;
 }
 
 // One thread per output Pi[ta][tb][d0 + K0][d1 + K1].
@@ -314,7 +330,24 @@ __global__ void __launch_bounds__(256) lagfix_kernel(Geom g, int mode, const dou
 template <typename Tin>
 hipError_t launch_polyrow(const Geom& g, const Tin* img, int da, int dbb, int K1, double* vrow,
                           hipStream_t st) {
-    hipLaunchKernelGGL(polyrow_kernel<Tin>, dim3(g.n0), dim3(256), 0, st, g, img, da, dbb, K1, vrow);
+    const dim3 grid((g.n0 + 3) / 4), block(256);
+    switch (da + dbb + 1) {
+#define SFFT_POLYROW(NE)                                                                        \
+    case NE:                                                                                    \
+        hipLaunchKernelGGL((polyrow_kernel<Tin, NE>), grid, block, 0, st, g, img, da, dbb, K1, vrow); \
+        break;
+        SFFT_POLYROW(1)
+        SFFT_POLYROW(2)
+        SFFT_POLYROW(3)
+        SFFT_POLYROW(4)
+        SFFT_POLYROW(5)
+        SFFT_POLYROW(6)
+        SFFT_POLYROW(7)
+        SFFT_POLYROW(8)
+        SFFT_POLYROW(9)
+#undef SFFT_POLYROW
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -323,12 +356,12 @@ hipError_t launch_polycorr(const Geom& g, const double* vrow, int da, int dbb, i
     const int nta = (da + 1) * (da + 2) / 2, ntb = (dbb + 1) * (dbb + 2) / 2;
     const int nitem = (da + 1) * (dbb + 1) * (2 * K1 + 1);
     const int ne = da + dbb + 1;
-    const int nchunk = (g.n0 + kRowChunk - 1) / kRowChunk;
+    const int nchunk = (g.n0 + kPolyRowChunk - 1) / kPolyRowChunk;
     // part holds nchunk * ne * nitem partial moments, then ne * nitem sums
     double* mom = part + (size_t)nchunk * ne * nitem;
     hipLaunchKernelGGL(polymom_kernel, dim3(nchunk), dim3(256), 0, st, g, vrow, nitem, ne, part);
     const int nval = ne * nitem;
-    hipLaunchKernelGGL(momsum_kernel, dim3((nval + 255) / 256), dim3(256), 0, st, nchunk, nval, part,
+    hipLaunchKernelGGL(momsum_kernel, dim3((nval + 3) / 4), dim3(256), 0, st, nchunk, nval, part,
                        mom);
     const int nout = nta * ntb * (2 * K0 + 1) * (2 * K1 + 1);
     hipLaunchKernelGGL(polycorr_kernel, dim3((nout + 255) / 256), dim3(256), 0, st, g, vrow, mom, da,

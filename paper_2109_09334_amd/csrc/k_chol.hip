@@ -3,8 +3,9 @@
 // Jacobi scaling d = diag(G)^-1/2 keeps the factor well scaled; the scaled
 // matrix D G D is factorised by a blocked right-looking Cholesky (64-wide
 // panels: the diagonal block is factorised and the panel below it solved
-// against that factor in one register-tiled pass, the trailing lower
-// triangle updated by 64x64 FP64 tiles), then L y = D b and L^T z = y are solved with 64-row blocks and
+// against that factor in one register-tiled pass; each panel's update of the
+// trailing lower triangle, in 64x64 FP64 tiles, runs in the next panel's
+// launch), then L y = D b and L^T z = y are solved with 64-row blocks and
 // c = D z. A non-positive or non-finite pivot sets a device flag instead of
 // stopping; the host reports it and the coefficients are set to NaN.
 #include "kernels.hpp"
@@ -47,22 +48,85 @@ __global__ void __launch_bounds__(256) scale_kernel(int n, const double* __restr
     if (bad) atomicOr(flag, kFlagNonFinite);
 }
 
-// One launch per 64-wide panel at column kb. Every workgroup factorises the
-// panel's diagonal block D (L is not written there during the launch, so all
-// workgroups see the same input and compute the same factor); workgroup 0
-// stores it in dfac (copied into L after the last panel), workgroup b >= 1
-// also solves row block b of the panel, X L_D^T = A. Both run as one
-// right-looking pass over the 64 columns: 256 threads own 4x4 register tiles
-// (rows ty + 16 a, columns tx + 16 b) of D and of A; the raw column j is
-// published through LDS (double buffered, so one barrier per column) and
-// every thread scales it by the pivot itself before its rank-1 update. The
-// column group bj = j / 16 is a compile-time index (the loop over it is
-// unrolled), so the owners address their tile registers statically and the
-// updates skip the column groups left of the pivot.
-__global__ void __launch_bounds__(256) panel_kernel(int n, double* __restrict__ L, int kb,
-                                                     double* __restrict__ dfac, int* flag) {
+// A_(i0.., j0..) -= L_(i0.., kp..kp+63) L_(j0.., kp..kp+63)^T on one 64 x 64
+// tile of the lower triangle (diag: i0 == j0, only c <= i is stored).
+__device__ __forceinline__ void tile_update(int n, double* __restrict__ L, int kp, int i0, int j0,
+                                            double (*PI)[NBK + 1], double (*PJ)[NBK + 1]) {
+    const int ni = min(NBK, n - i0), nj = min(NBK, n - j0);
+    for (int t = threadIdx.x; t < NBK * NBK; t += blockDim.x) {
+        const int i = t >> 6, c = t & 63;
+        PI[i][c] = i < ni ? L[(size_t)(i0 + i) * n + kp + c] : 0.0;
+        PJ[i][c] = i < nj ? L[(size_t)(j0 + i) * n + kp + c] : 0.0;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int c = 0; c < NBK; ++c) {
+        double x[4], y[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            x[a] = PI[ty + 16 * a][c];
+            y[a] = PJ[tx + 16 * a][c];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int i = ty + 16 * a;
+        if (i >= ni) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int jc = tx + 16 * b;
+            if (jc >= nj || (i0 == j0 && jc > i)) continue;
+            L[(size_t)(i0 + i) * n + j0 + jc] -= acc[a][b];
+        }
+    }
+}
+
+// Step k of the right-looking factorisation, with the trailing update of
+// step k - 1 folded in: one launch per 64-column panel (kb = 64 k).
+//  * Workgroups b < T - k (T = number of 64-blocks) work on panel k, row
+//    block k + b. For k > 0 they first apply panel k-1's update to their own
+//    tile of column block k and to the diagonal tile (in registers: every
+//    panel workgroup forms the updated diagonal tile itself, nothing is
+//    written there during the launch). Then every one factorises the
+//    diagonal block D; workgroup 0 stores it in dfac (copied into L after
+//    the last step), workgroup b >= 1 also solves its row block X L_D^T = A.
+//    Factor and solve are one right-looking pass over the 64 columns: 256
+//    threads own 4x4 register tiles (rows ty + 16 a, columns tx + 16 b) of D
+//    and A; the raw column j is published through LDS (double buffered, one
+//    barrier per column) and every thread scales it by the pivot itself. The
+//    column group bj = j / 16 is unrolled, so tiles are addressed statically
+//    and the updates skip the groups left of the pivot.
+//  * The other workgroups give the tiles (I, J), I >= J > k, of the trailing
+//    matrix panel k-1's update.
+// After the launch column block k is final and every tile right of it has
+// the updates of panels 0 .. k-1.
+__global__ void __launch_bounds__(256) chol_step_kernel(int n, double* __restrict__ L, int k,
+                                                         double* __restrict__ dfac, int* flag) {
+    __shared__ double PI[NBK][NBK + 1];
+    __shared__ double PJ[NBK][NBK + 1];
     __shared__ double colD[2][NBK];
     __shared__ double colA[2][NBK];
+    const int T = (n + NBK - 1) / NBK;
+    const int kb = k * NBK;
+    const int npan = T - k;
+    if ((int)blockIdx.x >= npan) {
+        int I = 0, rem = blockIdx.x - npan;
+        while (rem > I) {
+            rem -= I + 1;
+            ++I;
+        }
+        tile_update(n, L, kb - NBK, (k + 1 + I) * NBK, (k + 1 + rem) * NBK, PI, PJ);
+        return;
+    }
     const int nb = min(NBK, n - kb);
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int r0 = kb + blockIdx.x * NBK;
@@ -76,6 +140,32 @@ __global__ void __launch_bounds__(256) panel_kernel(int n, double* __restrict__ 
             d[a][b] = (i < nb && c <= i) ? L[(size_t)(kb + i) * n + kb + c] : 0.0;
             x[a][b] = (i < nr && c < nb) ? L[(size_t)(r0 + i) * n + kb + c] : 0.0;
         }
+    if (k > 0) {
+        // panel k-1 (64 full columns at kp) onto D and onto this row block
+        const int kp = kb - NBK;
+        for (int t = threadIdx.x; t < NBK * NBK; t += blockDim.x) {
+            const int i = t >> 6, c = t & 63;
+            PJ[i][c] = i < nb ? L[(size_t)(kb + i) * n + kp + c] : 0.0;
+            PI[i][c] = i < nr ? L[(size_t)(r0 + i) * n + kp + c] : 0.0;
+        }
+        __syncthreads();
+        for (int c = 0; c < NBK; ++c) {
+            double pr[4], pc[4], qr[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                pr[a] = PJ[ty + 16 * a][c];
+                pc[a] = PJ[tx + 16 * a][c];
+                qr[a] = PI[ty + 16 * a][c];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    d[a][b] -= pr[a] * pc[b];
+                    x[a][b] -= qr[a] * pc[b];
+                }
+        }
+    }
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) {
 #pragma unroll 1
@@ -131,7 +221,7 @@ __global__ void __launch_bounds__(256) panel_kernel(int n, double* __restrict__ 
         }
     }
     if (blockIdx.x == 0) {
-        double* out = dfac + (size_t)(kb / NBK) * NBK * NBK;
+        double* out = dfac + (size_t)k * NBK * NBK;
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -242,56 +332,6 @@ __global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__
     }
 }
 
-// Trailing update of the lower triangle: tile (I, J), I >= J, of the rows
-// and columns after the panel: A_IJ -= L_I,panel L_J,panel^T.
-__global__ void __launch_bounds__(256) syrk_kernel(int n, double* __restrict__ L, int kb) {
-    __shared__ double PI[NBK][NBK + 1];
-    __shared__ double PJ[NBK][NBK + 1];
-    const int nb = min(NBK, n - kb);
-    const int t0 = kb + nb;
-    // triangular tile index -> (I, J)
-    int I = 0, rem = blockIdx.x;
-    while (rem > I) { rem -= I + 1; ++I; }
-    const int J = rem;
-    const int i0 = t0 + I * NBK, j0 = t0 + J * NBK;
-    const int ni = min(NBK, n - i0), nj = min(NBK, n - j0);
-    for (int t = threadIdx.x; t < NBK * NBK; t += blockDim.x) {
-        const int i = t >> 6, c = t & 63;
-        PI[i][c] = (i < ni && c < nb) ? L[(size_t)(i0 + i) * n + kb + c] : 0.0;
-        PJ[i][c] = (i < nj && c < nb) ? L[(size_t)(j0 + i) * n + kb + c] : 0.0;
-    }
-    __syncthreads();
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;   // 16 x 16 threads, 4x4 each
-    double acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int c = 0; c < nb; ++c) {
-        double x[4], y[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            x[a] = PI[ty + 16 * a][c];
-            y[a] = PJ[tx + 16 * a][c];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int i = ty + 16 * a;
-        if (i >= ni) continue;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int j = tx + 16 * b;
-            if (j >= nj || (I == J && j > i)) continue;
-            L[(size_t)(i0 + i) * n + j0 + j] -= acc[a][b];
-        }
-    }
-}
-
 // Row block of the left-looking triangular sweep: for the nb rows r0 + i,
 //   u_i = y[r0 + i] - sum_(c in [c_lo, c_hi)) M[(r0 + i) n + c] y[c],
 // then y[r0 + i] = sum_k W[i][k] u_k (W: 64 x 64 row-major). y lives in LDS.
@@ -383,17 +423,13 @@ hipError_t launch_jacobi(int n, const double* G, const double* h, double* L, dou
 }
 
 hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* flag, hipStream_t st) {
-    for (int kb = 0; kb < n; kb += NBK) {
-        const int nblk = (n - kb + NBK - 1) / NBK;
-        hipLaunchKernelGGL(panel_kernel, dim3(nblk), dim3(256), 0, st, n, L, kb, dfac, flag);
-        const int nb = min(NBK, n - kb);
-        const int rest = n - kb - nb;
-        if (rest > 0) {
-            const int T = (rest + NBK - 1) / NBK;
-            hipLaunchKernelGGL(syrk_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, st, n, L, kb);
-        }
-    }
     const int T = (n + NBK - 1) / NBK;
+    for (int k = 0; k < T; ++k) {
+        const int npan = T - k;
+        const int ntrail = k > 0 ? (T - k - 1) * (T - k) / 2 : 0;
+        hipLaunchKernelGGL(chol_step_kernel, dim3(npan + ntrail), dim3(256), 0, st, n, L, k, dfac,
+                           flag);
+    }
     hipLaunchKernelGGL(diag_finish_kernel, dim3(T), dim3(256), 0, st, n, L, dfac, dinv);
     if (T > 1) hipLaunchKernelGGL(mirror_kernel, dim3(T * (T - 1) / 2), dim3(256), 0, st, n, L);
     return hipGetLastError();

@@ -18,7 +18,7 @@ __device__ __forceinline__ cx<T>* lds_base() {
     return reinterpret_cast<cx<T>*>(smem_raw);
 }
 
-template <typename T, typename Tin>
+template <typename T, typename Tin, typename PL>
 __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSources src,
                                                       const Tin* __restrict__ img0,
                                                       const Tin* __restrict__ img1,
@@ -32,6 +32,7 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
     const int n1 = g.n1;
     cx<T>* buf = lds + line * line_lds_elems(n1);
     const int npk = (src.n + 1) / 2;
+#pragma unroll 1
     for (int pk = 0; pk < npk; ++pk) {
         const int ia = 2 * pk, ib = 2 * pk + 1;
         const bool hasb = ib < src.n;
@@ -54,7 +55,7 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e) v[e] = mk(T(0), T(0));
         }
-        line_fft_regs<-1, T>(v, buf, lp, lt, twt);
+        line_fft<-1, T, PL>(v, buf, lp, lt, twt);
         // separate the two real rows: needs X(m) and X(N1 - m) together
         __syncthreads();
 #pragma unroll
@@ -63,6 +64,7 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
         if (act) {
             cx<T>* za = Z + ((size_t)src.out[ia] * g.n0 + row) * g.hp;
             cx<T>* zb = Z + ((size_t)(hasb ? src.out[ib] : 0) * g.n0 + row) * g.hp;
+#pragma unroll 2
             for (int m = lt; m < g.h; m += lp.tl) {
                 const cx<T> a = buf[lpad(m)], b = buf[lpad(m == 0 ? 0 : n1 - m)];
                 za[m] = mk((a.re + b.re) * T(0.5), (a.im - b.im) * T(0.5));
@@ -73,7 +75,7 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
     }
 }
 
-template <typename T>
+template <typename T, typename PL>
 __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJobs jobs,
                                                       const cx<T>* __restrict__ Z,
                                                       cx<T>* __restrict__ X,
@@ -100,6 +102,7 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
         for (int e = 0; e < kElemsPerThread; ++e) z[e] = zc[(size_t)(lt + e * lp.tl) * g.hp];
     }
     const int nw = jobs.nw[job];
+#pragma unroll 1
     for (int i = 0; i < nw; ++i) {
         cx<T> v[kElemsPerThread];
 #pragma unroll
@@ -107,7 +110,7 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
             const int x0 = lt + e * lp.tl;
             v[e] = act ? cscale(z[e], ipow(coord<T>(x0, n0), i)) : mk(T(0), T(0));
         }
-        line_fft_regs<-1, T>(v, buf, lp, lt, twt);
+        line_fft<-1, T, PL>(v, buf, lp, lt, twt);
         if (act) {
             cx<T>* xo = X + ((size_t)jobs.spec[job][i] * g.h + m) * n0;
 #pragma unroll
@@ -120,7 +123,7 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
 // complex line (Hermitian extension of each half spectrum). sky is the FP64
 // table of sky_kernel: sum_r c0(x0)^r Y_r(x1) on rows w0 <= x0 < N0 - w0,
 // tabulated rows on the 2 w0 edge rows.
-template <typename T, typename Tout>
+template <typename T, typename Tout, typename PL>
 __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
                                                       const cx<T>* __restrict__ Dt,
                                                       Tout* __restrict__ d,
@@ -155,7 +158,7 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) v[e] = mk(T(0), T(0));
     }
-    line_fft_regs<1, T>(v, buf, lp, lt, twt);
+    line_fft<1, T, PL>(v, buf, lp, lt, twt);
     if (act) {
         const double inv = 1.0 / (double)n1;
         const int n0 = g.n0, w0 = g.w0, R = max(g.dk, g.db);
@@ -186,7 +189,7 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
     }
 }
 
-template <typename T, int S>
+template <typename T, int S, typename PL>
 __global__ void __launch_bounds__(512) fft_lines_kernel(LinePlan lp, int nlines,
                                                          const cx<T>* __restrict__ in,
                                                          cx<T>* __restrict__ out,
@@ -200,7 +203,7 @@ __global__ void __launch_bounds__(512) fft_lines_kernel(LinePlan lp, int nlines,
 #pragma unroll
     for (int e = 0; e < kElemsPerThread; ++e)
         v[e] = act ? in[(size_t)ln * lp.n + lt + e * lp.tl] : mk(T(0), T(0));
-    line_fft_regs<S, T>(v, buf, lp, lt, twt);
+    line_fft<S, T, PL>(v, buf, lp, lt, twt);
     if (act)
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) out[(size_t)ln * lp.n + lt + e * lp.tl] = v[e];
@@ -221,37 +224,44 @@ hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& sr
                          const Tin* img1, const double* ped, cx<T>* Z, const cx<T>* twt,
                          hipStream_t st) {
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
-    auto k = rowfwd_kernel<T, Tin>;
-    hipError_t e = set_lds(k, lds);
-    if (e != hipSuccess) return e;
     dim3 grid((g.n0 + lp.lpw - 1) / lp.lpw);
-    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, src, img0, img1, ped, Z, twt);
-    return hipGetLastError();
+    return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
+        auto k = rowfwd_kernel<T, Tin, decltype(pl)>;
+        hipError_t e = set_lds(k, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, src, img0, img1, ped, Z,
+                           twt);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
 hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs, const cx<T>* Z,
                          cx<T>* X, const cx<T>* twt, hipStream_t st) {
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
-    auto k = colfwd_kernel<T>;
-    hipError_t e = set_lds(k, lds);
-    if (e != hipSuccess) return e;
     const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
     dim3 grid((ncb + 127) / 128 * 128 * jobs.narr);
-    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, jobs, Z, X, twt);
-    return hipGetLastError();
+    return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
+        auto k = colfwd_kernel<T, decltype(pl)>;
+        hipError_t e = set_lds(k, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, jobs, Z, X, twt);
+        return hipGetLastError();
+    });
 }
 
 template <typename T, typename Tout>
 hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, Tout* d,
                          const double* sky, const cx<T>* twt, hipStream_t st) {
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
-    auto k = rowinv_kernel<T, Tout>;
-    hipError_t e = set_lds(k, lds);
-    if (e != hipSuccess) return e;
     dim3 grid((g.n0 / 2 + lp.lpw - 1) / lp.lpw);
-    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, Dt, d, sky, twt);
-    return hipGetLastError();
+    return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
+        auto k = rowinv_kernel<T, Tout, decltype(pl)>;
+        hipError_t e = set_lds(k, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, Dt, d, sky, twt);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
@@ -259,18 +269,13 @@ hipError_t launch_fft_lines(const LinePlan& lp, int nlines, int sign, const cx<T
                             const cx<T>* twt, hipStream_t st) {
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     dim3 grid((nlines + lp.lpw - 1) / lp.lpw);
-    if (sign < 0) {
-        auto k = fft_lines_kernel<T, -1>;
+    return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
+        auto k = sign < 0 ? fft_lines_kernel<T, -1, decltype(pl)> : fft_lines_kernel<T, 1, decltype(pl)>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, lp, nlines, in, out, twt);
-    } else {
-        auto k = fft_lines_kernel<T, 1>;
-        hipError_t e = set_lds(k, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, lp, nlines, in, out, twt);
-    }
-    return hipGetLastError();
+        return hipGetLastError();
+    });
 }
 
 #define SFFT_INST_T(T)                                                                            \

@@ -35,7 +35,7 @@ __host__ __device__ __forceinline__ void decode_pair(int P, int pr, int& kb, int
     k = kb + c;
 }
 
-template <typename T>
+template <typename T, typename PL>
 __global__ void __launch_bounds__(512) lagcol_kernel(Geom g, LinePlan lp, int p0, int np, int sslot,
                                                       const cx<T>* __restrict__ X,
                                                       cx<T>* __restrict__ Cl,
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(512) lagcol_kernel(Geom g, LinePlan lp, int p0
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) v[e] = mk(T(0), T(0));
     }
-    line_fft_regs<1, T>(v, buf, lp, lt, twt);
+    line_fft<1, T, PL>(v, buf, lp, lt, twt);
     if (act) {
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) {
@@ -119,7 +119,25 @@ __device__ __forceinline__ void wave_transpose_sum16(cx<T>* v, int lane) {
     v[0].im += __shfl_xor(v[0].im, 1, 64);
 }
 
-template <typename T>
+// Table index of the twiddle of slot r in lag block tb, e^(-2 pi i j t / N0)
+// with t the lag the slot carries, t = tb + ((r - tb) mod 16); |j t| < 3 N0
+// (|t| <= 4 w0 + 15, j < N0/16, 4 w0 < N0).
+__device__ __forceinline__ int lag_twiddle_index(int n0, int j, int tb, int r) {
+    const int mres = tb & 15;
+    const int t = tb - mres + r + (r < mres ? 16 : 0);
+    int idx = j * t;
+#pragma unroll
+    for (int c3 = 0; c3 < 3; ++c3) idx += idx < 0 ? n0 : 0;
+#pragma unroll
+    for (int c3 = 0; c3 < 3; ++c3) idx -= idx >= n0 ? n0 : 0;
+    return idx;
+}
+
+// NB > 0: the Omega lags span NB blocks of 16 and the thread's 16 NB
+// twiddle-table indices are formed once and kept in registers (Theta's lags
+// lie in the same range at the same slot residues, so they select from
+// them); NB = 0: indices are formed per product and block.
+template <typename T, int NB>
 __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, int ir_only,
                                                            int sslot, int pchunk,
                                                            const cx<T>* __restrict__ X,
@@ -146,6 +164,13 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
 #pragma unroll
         for (int q = 0; q < 16; ++q) a[q] = A[(size_t)q * tl];
     }
+    int twi[NB > 0 ? NB : 1][16];
+    if constexpr (NB > 0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) twi[b][r] = lag_twiddle_index(n0, j, -KO + 16 * b, r);
+    }
     const int kfirst = ir_only ? g.P : kb;
     for (int k0 = kfirst; k0 <= g.P; k0 += pchunk) {
         const int k1 = min(g.P + 1, k0 + pchunk);
@@ -165,19 +190,25 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
             }
             for (int blk = 0; 16 * blk <= 2 * K; ++blk) {
                 const int tb = -K + 16 * blk;
-                const int mres = tb & 15;
                 cx<T> s[16];
+                if constexpr (NB > 0) {
+                    // Omega: block blk; Theta: slot r's lag t lies in Omega
+                    // block (t + KO) / 16 at the same slot
+                    const int mres = tb & 15;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    // slot r carries lag t = tb + ((r - tb) mod 16)
-                    // (|t| <= 4 w0 + 15 and j < N0/16 with 4 w0 < N0: |j t| < 3 N0)
-                    const int t = tb - mres + r + (r < mres ? 16 : 0);
-                    int idx = j * t;
+                    for (int r = 0; r < 16; ++r) {
+                        const int t = tb - mres + r + (r < mres ? 16 : 0);
+                        const int ob = theta ? (t + KO) >> 4 : blk;
+                        int idx = twi[0][r];
 #pragma unroll
-                    for (int c3 = 0; c3 < 3; ++c3) idx += idx < 0 ? n0 : 0;
+                        for (int b = 1; b < NB; ++b)
+                            if (b == ob) idx = twi[b][r];
+                        s[r] = cmul(v[r], cconj(tw[idx]));   // e^(+2 pi i j t / N0)
+                    }
+                } else {
 #pragma unroll
-                    for (int c3 = 0; c3 < 3; ++c3) idx -= idx >= n0 ? n0 : 0;
-                    s[r] = cmul(v[r], cconj(tw[idx]));   // e^(+2 pi i j t / N0)
+                    for (int r = 0; r < 16; ++r)
+                        s[r] = cmul(v[r], cconj(tw[lag_twiddle_index(n0, j, tb, r)]));
                 }
                 wave_transpose_sum16(s, lane);
                 if ((lane & 3) == 0)
@@ -296,21 +327,26 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
         const size_t per = (size_t)nblk * nwv * 16 * sizeof(cx<T>);
         const int pchunk = (int)std::max<size_t>(1, std::min<size_t>(g.P + 1, 32768 / per));
         dim3 grid((ncb + 7) / 8 * 8 * g.P);
-        hipLaunchKernelGGL(lagcol_tail_kernel<T>, grid, dim3(lp.tl * lp.lpw), pchunk * per, st, g,
-                           lp, p0 == 0 ? 0 : 1, sslot, pchunk, X, Cl, tw);
+        auto k = nblk == 1 ? lagcol_tail_kernel<T, 1>
+                 : nblk == 2 ? lagcol_tail_kernel<T, 2> : lagcol_tail_kernel<T, 0>;
+        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), pchunk * per, st, g, lp, p0 == 0 ? 0 : 1,
+                           sslot, pchunk, X, Cl, tw);
         return hipGetLastError();
     }
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
-    auto k = lagcol_kernel<T>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
     const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
     dim3 grid((ncb + 7) / 8 * 8 * (p1 - p0));
-    hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, p0, p1 - p0, sslot, X, Cl, twt);
-    return hipGetLastError();
+    return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
+        auto k = lagcol_kernel<T, decltype(pl)>;
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, p0, p1 - p0, sslot, X, Cl,
+                           twt);
+        return hipGetLastError();
+    });
 }
 
 template <typename T>

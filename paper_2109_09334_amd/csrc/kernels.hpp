@@ -61,10 +61,11 @@ hipError_t launch_polyrow(const Geom& g, const Tin* img, int da, int dbb, int K1
 // part: scratch of polycorr_part_len(g, da, dbb, K1) doubles.
 hipError_t launch_polycorr(const Geom& g, const double* vrow, int da, int dbb, int K0, int K1,
                            double* part, double* pi, hipStream_t st);
+constexpr int kPolyRowChunk = 16;   // rows per partial-moment chunk
 inline size_t polycorr_part_len(const Geom& g, int da, int dbb, int K1) {
     const size_t nitem = (size_t)(da + 1) * (dbb + 1) * (2 * K1 + 1);
     const size_t ne = da + dbb + 1;
-    return ((size_t)(g.n0 + 63) / 64 + 1) * ne * nitem;
+    return ((size_t)(g.n0 + kPolyRowChunk - 1) / kPolyRowChunk + 1) * ne * nitem;
 }
 hipError_t launch_polysum(const Geom& g, int dmax, double* sig0, double* sig1, double* pw,
                           hipStream_t st);
