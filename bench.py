@@ -50,6 +50,20 @@ def load_pair(n, nstars):
     return p.r, p.s
 
 
+def cached_pair(tag, make):
+    """(r, s) of a generated pair, cached under /tmp for reruns on one box."""
+    path = f"/tmp/sfft_bench_{tag}.npz"
+    if os.path.exists(path):
+        z = np.load(path)
+        return z["r"], z["s"]
+    p = make()
+    try:
+        np.savez(path, r=p.r, s=p.s)
+    except OSError:
+        pass
+    return p.r, p.s
+
+
 def stage_work(g, stage, s_cx):
     """Algorithmic (bytes, flops) of one call of a stage; s_cx = bytes per
     complex value of the transforms. FFT flops use the 5 N log2 N convention;
@@ -153,7 +167,12 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--stars", type=int, default=40000)
-    ap.add_argument("--stream-requests", type=int, default=120)
+    ap.add_argument("--stream-requests", type=int, default=200,
+                    help="requests per load point of the serving stream (plus 10 %% warm-up)")
+    ap.add_argument("--mix-batch", type=int, default=48,
+                    help="requests of the closed-loop run that sets the saturated rate of the mix")
+    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-c4", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -224,32 +243,115 @@ def main():
         dt = time.perf_counter() - t
         return steps * batch / dt, dt, outs[0]
 
-    def stream_latency(p, rate, count):
-        outs = [(torch.empty(nu, dtype=torch.float64, device=dev),
-                 torch.empty((n, n), dtype=torch.float32, device=dev)) for _ in range(16)]
-        rng = np.random.default_rng(7)
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, count))
-        lat = []
-        pending = {}
+    # ---- the serving mix (C5): 60 % 2048^2, 30 % 4096^2, 10 % 6144^2, kernel
+    # half-width 5 or 7, DK = DB = 2. One rendered pair per shape, reused by
+    # every request of that shape (the inputs only need the right shape and
+    # statistics; each request runs the whole path).
+    import datagen
+    mix_pairs = {}
+    for (shape, _) in datagen.STREAM_SHAPES:
+        if args.no_stream:
+            break
+        t0 = time.time()
+        pr = cached_pair(f"mix_{shape[0]}x{shape[1]}",
+                         lambda shape=shape: datagen.star_pair(1000 + shape[0], *shape, w=7, dk=2, db=2))
+        mix_pairs[shape] = (torch.from_numpy(pr[0]).to(dev), torch.from_numpy(pr[1]).to(dev))
+        log(f"[bench] mix pair {shape} ready in {time.time() - t0:.1f}s")
+
+    def mix_requests(count, seed):
+        return datagen.stream_requests(count, seed=seed)
+
+    def mix_params(rq, prec):
+        (n0, n1), w = rq["shape"], rq["w"]
+        return sf.Params(n0, n1, w, w, rq["dk"], rq["db"], 0, prec, sf.F32)
+
+    out_pool = {}
+
+    def take_out(p):
+        key = (p.n0, p.n1, p.num_unknowns)
+        lst = out_pool.setdefault(key, [])
+        if lst:
+            return lst.pop()
+        return (torch.empty(p.num_unknowns, dtype=torch.float64, device=dev),
+                torch.empty((p.n0, p.n1), dtype=torch.float32, device=dev))
+
+    def give_out(p, o):
+        out_pool[(p.n0, p.n1, p.num_unknowns)].append(o)
+
+    def mix_saturated(prec, count):
+        """Closed-loop rate of the mix: every request submitted at once."""
+        ctx.engine_config(args.slots)
+        rqs = mix_requests(count, seed=11)
+        ps = [mix_params(rq, prec) for rq in rqs]
+        outs = [take_out(p) for p in ps]
+        t = time.perf_counter()
+        tk = [ctx.submit(p, *mix_pairs[rq["shape"]], *mix_pairs[rq["shape"]], *o)
+              for p, rq, o in zip(ps, rqs, outs)]
+        for x in tk:
+            ctx.wait(x)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        for p, o in zip(ps, outs):
+            give_out(p, o)
+        return count / dt
+
+    def mix_stream(prec, rate, count, warm):
+        """Poisson arrivals at `rate`; latency = completion - arrival, host
+        clock, queueing included; the first `warm` requests are not counted."""
+        ctx.engine_config(args.slots)
+        rqs = mix_requests(count + warm, seed=7)
+        arrivals = datagen.poisson_arrivals(count + warm, rate, seed=7)
+        lat, pending = [], {}
         t_start = time.perf_counter()
         i = 0
-        free = list(range(len(outs)))
-        while i < count or pending:
+        while i < len(rqs) or pending:
             now = time.perf_counter() - t_start
-            while i < count and arrivals[i] <= now and free:
-                k = free.pop()
-                c, d = outs[k]
-                tk = ctx.submit(p, R, S, R, S, c, d)
-                pending[tk] = (arrivals[i], k)
+            while i < len(rqs) and arrivals[i] <= now:
+                rq = rqs[i]
+                p = mix_params(rq, prec)
+                o = take_out(p)
+                R_, S_ = mix_pairs[rq["shape"]]
+                tk = ctx.submit(p, R_, S_, R_, S_, *o)
+                pending[tk] = (arrivals[i], i, p, o)
                 i += 1
             for tk in list(pending):
                 if ctx.poll(tk) == sf.OK:
-                    arr, k = pending.pop(tk)
-                    lat.append(time.perf_counter() - t_start - arr)
-                    free.append(k)
+                    arr, k, p, o = pending.pop(tk)
+                    if k >= warm:
+                        lat.append(time.perf_counter() - t_start - arr)
+                    give_out(p, o)
             time.sleep(5e-5)
         lat = np.array(lat) * 1e3
-        return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+        return {"rate_per_s": rate, "requests": count, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99))}
+
+    def c4_batch():
+        """C4: 64 ragged pairs (512^2 .. 2048x4096, w = 5, DK = DB = 1) served
+        as one batch through the engine (mixed form)."""
+        ctx.engine_config(args.slots)
+        pairs = {}
+        for shp in datagen.BATCH_SHAPES:
+            pr = cached_pair(f"c4_{shp[0]}x{shp[1]}",
+                             lambda shp=shp: datagen.star_pair(100 + shp[0] + shp[1], *shp, w=5, dk=1, db=1))
+            pairs[shp] = (torch.from_numpy(pr[0]).to(dev), torch.from_numpy(pr[1]).to(dev))
+        rng = np.random.default_rng(100)
+        picks = [datagen.BATCH_SHAPES[k] for k in rng.integers(0, len(datagen.BATCH_SHAPES), 64)]
+        ps = [sf.Params(a, b_, 5, 5, 1, 1, 0, sf.MIXED, sf.F32) for (a, b_) in picks]
+        outs = [(torch.empty(p.num_unknowns, dtype=torch.float64, device=dev),
+                 torch.empty((p.n0, p.n1), dtype=torch.float32, device=dev)) for p in ps]
+
+        def once():
+            tk = [ctx.submit(p, *pairs[s], *pairs[s], *o) for p, s, o in zip(ps, picks, outs)]
+            for x in tk:
+                ctx.wait(x)
+            torch.cuda.synchronize()
+
+        once()   # plans and workspaces
+        t = time.perf_counter()
+        once()
+        dt = time.perf_counter() - t
+        return {"pairs": 64, "pairs_per_s": 64 / dt, "ms": dt * 1e3,
+                "mpix_per_s": sum(p.n0 * p.n1 for p in ps) / dt / 1e6}
 
     # ---- served throughput: mixed form (headline), then FP64 form
     thr_m, dt_m, (coef_m, d_m) = served(pm, args.steps, args.warmup, args.batch)
@@ -264,12 +366,24 @@ def main():
         dd = (d_m.double() - d_64.double())
         res64["mixed_vs_fp64_d_rms"] = float(torch.sqrt(torch.mean(dd * dd)).item())
 
-    # ---- latency under a Poisson stream at ~70 % of the measured throughput
-    p50, p99 = stream_latency(pm, 0.7 * thr_m, args.stream_requests)
-    log(f"[bench] stream p50 {p50:.2f} ms p99 {p99:.2f} ms")
-    if res64 is not None:
-        q50, q99 = stream_latency(p64, 0.7 * res64["value"], max(40, args.stream_requests // 3))
-        res64.update({"p50_latency_ms": q50, "p99_latency_ms": q99})
+    # ---- latency under the C5 stream: saturated rate of the mix, then Poisson
+    # arrivals at 0.5 / 0.8 / 0.95 of it, both forms
+    stream = None
+    if not args.no_stream:
+        stream = {}
+        for name, prec in (("mixed", sf.MIXED), ("fp64", sf.FP64)):
+            if name == "fp64" and args.no_fp64:
+                continue
+            sat = mix_saturated(prec, args.mix_batch)
+            pts = {}
+            for frac in (0.5, 0.8, 0.95):
+                pts[str(frac)] = mix_stream(prec, frac * sat, args.stream_requests, args.stream_requests // 10)
+                log(f"[bench] {name} stream at {frac:.2f} x {sat:.1f}/s: p50 {pts[str(frac)]['p50_ms']:.2f} "
+                    f"ms p99 {pts[str(frac)]['p99_ms']:.2f} ms")
+            stream[name] = {"saturated_pairs_per_s": sat, "loads": pts}
+    c4 = None if args.no_c4 else c4_batch()
+    if c4:
+        log(f"[bench] C4 batch: {c4['pairs_per_s']:.1f} pairs/s")
 
     # ---- per-stage HIP-event times of direct calls (same stream as the kernels)
     def stages(p, iters=3):
@@ -299,6 +413,10 @@ def main():
     dom = max(stage_roof.values(), key=lambda r: r["kernel_ms"])
     roof = dict(dom)
     roof["traffic"] = measured_traffic(dom["kernel"])
+
+    # pipeline roofline: algorithmic bytes per pair of build + subtract
+    # ((3 DK + 11) s n) plus the refinement pass ((DK + 4) s n), s = 4 B
+    balg = float((3 * dk + 11 + dk + 4) * 4 * n * n)
 
     # ---- CPU baseline: the FP64 oracle on a bounded crop of the same pair
     cpu = None
@@ -335,9 +453,14 @@ def main():
                                f"15x15 kernel (w=7), DK=2, DB=2, {nu} unknowns",
                    "precision": "mixed: FP32 FFTs/products, FP64 lags/assembly/Cholesky/refinement",
                    "batch_per_step": args.batch, "engine_slots": args.slots},
-        "p50_latency_ms": p50,
-        "p99_latency_ms": p99,
-        "stream_rate_per_s": 0.7 * thr_m,
+        "p50_latency_ms": stream["mixed"]["loads"]["0.8"]["p50_ms"] if stream else None,
+        "p99_latency_ms": stream["mixed"]["loads"]["0.8"]["p99_ms"] if stream else None,
+        "latency_note": "C5 stream (60/30/10 % 2048^2/4096^2/6144^2, w 5 or 7, DK=DB=2), Poisson "
+                        "arrivals at 0.8 x the saturated rate of the mix, mixed form",
+        "stream": stream,
+        "c4_batch": c4,
+        "pipeline_roofline": {"bytes_per_pair": balg, "achieved_gbs": thr_m * balg / 1e9,
+                              "frac": thr_m * balg / 1e9 / HBM_PEAK_GBS},
         "fp64_form": res64,
         "stages_ms": {"mixed": st_m, "fp64": st_64},
         "roofline": roof,

@@ -236,6 +236,101 @@ __global__ void __launch_bounds__(256) stencil_kernel(Geom g, const cx<T>* __res
     }
 }
 
+// Register-resident stencil for compile-time (DK, W0): each thread owns NO
+// consecutive output rows of one column m and holds the NO + 2 W0 source rows
+// of each row spectrum Z_j in registers (read straight from HBM; neighbouring
+// threads of the same column share them through the caches), so every tap
+// is FMAs on registers:
+//   Dt(x0, m) = Z_S(x0, m) - sum_j sum_a0 Z_j(x0 - a0, m) poly_j(a0, m, x0 - a0),
+//   poly_j = sum_(i <= DK - j) Kt_(i,j)(a0, m) c0(x0 - a0)^i (Horner).
+// The block's stamp spectra (P x (2 W0 + 1) x 64 columns) are staged in LDS
+// once; a scheduling barrier between taps keeps the compiler from hoisting
+// every tap's stamp values into registers at once.
+// 64 columns x 4 row groups per 256-thread block.
+template <typename T, int DK, int W0, int NO>
+__global__ void __launch_bounds__(256) stencil_reg_kernel(Geom g, const cx<T>* __restrict__ Z,
+                                                           int zs, const cx<T>* __restrict__ Kt,
+                                                           cx<T>* __restrict__ Dt) {
+    constexpr int NS = NO + 2 * W0;
+    constexpr int L0 = 2 * W0 + 1;
+    constexpr int P = (DK + 1) * (DK + 2) / 2;
+    __shared__ cx<T> ktl[P * L0][64];
+    const int mc = threadIdx.x & 63;
+    const int m = blockIdx.x * 64 + mc;
+    const int x0b = (blockIdx.y * 4 + (threadIdx.x >> 6)) * NO;
+    const int n0 = g.n0;
+    const bool mok = m < g.h;
+    for (int t = threadIdx.x >> 6; t < P * L0; t += 4)
+        ktl[t][mc] = mok ? Kt[(size_t)t * g.hp + m] : mk(T(0), T(0));
+    __syncthreads();
+    if (!mok || x0b >= n0) return;   // no barriers below
+    const size_t plane = (size_t)n0 * g.hp;
+    int xs[NS];
+    T cs[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        xs[s] = imod(x0b - W0 + s, n0);
+        cs[s] = coord<T>(xs[s], n0);
+    }
+    cx<T> acc[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+        acc[o] = x0b + o < n0 ? Z[(size_t)zs * plane + (size_t)(x0b + o) * g.hp + m] : mk(T(0), T(0));
+#pragma unroll 1
+    for (int j = 0; j <= DK; ++j) {
+        constexpr int kMaxI = DK;
+        const cx<T>* Zj = Z + (size_t)j * plane + m;
+        cx<T> z[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) z[s] = Zj[(size_t)xs[s] * g.hp];
+        const int ni = DK - j;
+#pragma unroll
+        for (int a = 0; a < L0; ++a) {   // tap a0 = a - W0
+            cx<T> kt[kMaxI + 1];
+#pragma unroll
+            for (int i = 0; i <= kMaxI; ++i)
+                if (i <= ni) kt[i] = ktl[term_index(DK, i, j) * L0 + a][mc];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                const int s = o + 2 * W0 - a;   // source row x0 - a0
+                const T c = cs[s];
+                cx<T> poly = kt[ni];
+#pragma unroll
+                for (int i = kMaxI - 1; i >= 0; --i)
+                    if (i < ni) poly = mk(poly.re * c + kt[i].re, poly.im * c + kt[i].im);
+                acc[o] = acc[o] - cmul(poly, z[s]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+        if (x0b + o < n0) Dt[(size_t)(x0b + o) * g.hp + m] = acc[o];
+}
+
+template <typename T, int DK, int W0>
+static hipError_t launch_stencil_reg(const Geom& g, const cx<T>* Z, int zs, const cx<T>* Kt,
+                                     cx<T>* Dt, hipStream_t st) {
+    constexpr int NO = 8;
+    dim3 grid((g.h + 63) / 64, (g.n0 + 4 * NO - 1) / (4 * NO));
+    hipLaunchKernelGGL((stencil_reg_kernel<T, DK, W0, NO>), grid, dim3(256), 0, st, g, Z, zs, Kt, Dt);
+    return hipGetLastError();
+}
+
+// Specialised (DK, w0) pairs; false when the generic kernel must run.
+template <typename T, int DK>
+static bool stencil_reg_w(const Geom& g, const cx<T>* Z, int zs, const cx<T>* Kt, cx<T>* Dt,
+                          hipStream_t st, hipError_t* e) {
+    switch (g.w0) {
+        case 2: *e = launch_stencil_reg<T, DK, 2>(g, Z, zs, Kt, Dt, st); return true;
+        case 3: *e = launch_stencil_reg<T, DK, 3>(g, Z, zs, Kt, Dt, st); return true;
+        case 4: *e = launch_stencil_reg<T, DK, 4>(g, Z, zs, Kt, Dt, st); return true;
+        case 5: *e = launch_stencil_reg<T, DK, 5>(g, Z, zs, Kt, Dt, st); return true;
+        case 7: *e = launch_stencil_reg<T, DK, 7>(g, Z, zs, Kt, Dt, st); return true;
+        default: return false;
+    }
+}
+
 hipError_t launch_stamps(const Geom& g, const double* coef, double* kap, hipStream_t st) {
     hipLaunchKernelGGL(stamps_kernel, dim3(g.P), dim3(256), 0, st, g, coef, kap);
     return hipGetLastError();
@@ -252,11 +347,24 @@ hipError_t launch_stamp_spectra(const Geom& g, const double* kap, const double* 
 template <typename T>
 hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<T>* Kt, cx<T>* Dt,
                           hipStream_t st) {
+    hipError_t e = hipSuccess;
+    bool done = false;
+    // the register form for the FP32 transforms (in FP64 its register
+    // footprint spills for the larger kernels)
+    if constexpr (sizeof(T) == 4) {
+        switch (g.dk) {
+            case 0: done = stencil_reg_w<T, 0>(g, Z, zs_index, Kt, Dt, st, &e); break;
+            case 1: done = stencil_reg_w<T, 1>(g, Z, zs_index, Kt, Dt, st, &e); break;
+            case 2: done = stencil_reg_w<T, 2>(g, Z, zs_index, Kt, Dt, st, &e); break;
+            default: break;
+        }
+    }
+    if (done) return e;
     const size_t nsrc = kStTile + 2 * g.w0;
     const size_t lds = nsrc * kStCols * sizeof(cx<T>) + nsrc * sizeof(T);
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(stencil_kernel<T>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(stencil_kernel<T>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(stencil_kernel<T>, dim3((g.h + kStCols - 1) / kStCols, (g.n0 + kStTile - 1) / kStTile),
