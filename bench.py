@@ -186,6 +186,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    # Each engine slot runs on a HIP stream of its own. A process gets a fixed
+    # number of hardware queues (GPU_MAX_HW_QUEUES, 4 unless set) and streams
+    # that share one run one after another, so ask for one per slot beside
+    # the default stream's (read once, when HIP initialises: before torch).
+    hw_queues = max(8, args.slots + 2)
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < hw_queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, hw_queues))
+
     import torch
     import paper_2109_09334_amd as sf
 
@@ -452,7 +460,8 @@ def main():
         "config": {"workload": f"{n}x{n} FP32 star-field pair ({args.stars} Moffat stars), "
                                f"15x15 kernel (w=7), DK=2, DB=2, {nu} unknowns",
                    "precision": "mixed: FP32 FFTs/products, FP64 lags/assembly/Cholesky/refinement",
-                   "batch_per_step": args.batch, "engine_slots": args.slots},
+                   "batch_per_step": args.batch, "engine_slots": args.slots,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "p50_latency_ms": stream["mixed"]["loads"]["0.8"]["p50_ms"] if stream else None,
         "p99_latency_ms": stream["mixed"]["loads"]["0.8"]["p99_ms"] if stream else None,
         "latency_note": "C5 stream (60/30/10 % 2048^2/4096^2/6144^2, w 5 or 7, DK=DB=2), Poisson "

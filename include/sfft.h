@@ -193,7 +193,11 @@ typedef struct {
 
 /* Configure the engine: `slots` concurrent requests (each on its own HIP
  * stream with its own workspace), admission against the context's HBM
- * budget. Called once before the first submit; 0 slots = default (4). */
+ * budget. Called once before the first submit; 0 slots = default (4).
+ * Slots overlap on the device only if their streams sit on distinct hardware
+ * queues: HIP gives a process GPU_MAX_HW_QUEUES of them (4 unless set in the
+ * environment before HIP initialises), shared round robin by all streams,
+ * so a process serving `slots` requests wants at least slots + 1. */
 int sfft_engine_config(sfft_ctx* ctx, int slots);
 
 /* Queue a request. Returns SFFT_OK and a ticket; SFFT_E_NOMEM if the

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 namespace sfft {
 
@@ -93,30 +94,86 @@ __global__ void __launch_bounds__(512) lagcol_kernel(Geom g, LinePlan lp, int p0
 // carries and doubles the lanes each value is summed over), then across
 // waves through LDS. One block covers one column and one kernel term kb and
 // keeps conj(X_kb) in registers for all of that term's products.
-template <typename T, int HALF, int OFF>
-__device__ __forceinline__ void tr_step(cx<T>* v, int lane) {
-    const bool hi = (lane & OFF) != 0;
-#pragma unroll
-    for (int i = 0; i < HALF; ++i) {
-        cx<T> send = hi ? v[i] : v[i + HALF];
-        const cx<T> keep = hi ? v[i + HALF] : v[i];
-        send.re = __shfl_xor(send.re, OFF, 64);
-        send.im = __shfl_xor(send.im, OFF, 64);
-        v[i] = keep + send;
-    }
+// Lane exchanges of the transpose-reduce (CDNA4 VALU forms, no LDS):
+// swap32(a, b): a := [a(0..31) | b(0..31)], b := [a(32..63) | b(32..63)];
+// swap16(a, b): the same on 16-lane rows (odd rows of a <-> even rows of b);
+// dpp<CTRL>(x): x of lane L ^ 8 (row_ror:8), of lane 8 (L/8) + 7 - L%8
+// (row_half_mirror), of L ^ 1, of L ^ 2 (quad permutes).
+__device__ __forceinline__ void swap32(float& a, float& b) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap16(float& a, float& b) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap32(double& a, double& b) {
+    float2 x = __builtin_bit_cast(float2, a), y = __builtin_bit_cast(float2, b);
+    swap32(x.x, y.x);
+    swap32(x.y, y.y);
+    a = __builtin_bit_cast(double, x);
+    b = __builtin_bit_cast(double, y);
+}
+__device__ __forceinline__ void swap16(double& a, double& b) {
+    float2 x = __builtin_bit_cast(float2, a), y = __builtin_bit_cast(float2, b);
+    swap16(x.x, y.x);
+    swap16(x.y, y.y);
+    a = __builtin_bit_cast(double, x);
+    b = __builtin_bit_cast(double, y);
+}
+constexpr int kDppXor8 = 0x128, kDppHalfMirror = 0x141, kDppXor1 = 0xB1, kDppXor2 = 0x4E;
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+    float2 v = __builtin_bit_cast(float2, x);
+    v.x = dpp<CTRL>(v.x);
+    v.y = dpp<CTRL>(v.y);
+    return __builtin_bit_cast(double, v);
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ cx<T> dpp(cx<T> x) {
+    return mk(dpp<CTRL>(x.re), dpp<CTRL>(x.im));
 }
 
-// After the call lane L holds in v[0] the wave-wide sum of slot (L >> 2) & 15.
+// Wave-wide sums of 16 slots per lane. Every step halves the values a lane
+// carries and doubles the lanes each one is summed over: lanes L and L ^ 32,
+// then L ^ 16 (register swaps: each lane ends with its half of both), then
+// L ^ 8 and the mirror pair within 8 lanes (the lane sends the half it does
+// not keep), then the quad. After the call lane L holds in v[0] the sum of
+// slot (L >> 2) & 15 over the wave (all 64 lanes must be active).
 template <typename T>
 __device__ __forceinline__ void wave_transpose_sum16(cx<T>* v, int lane) {
-    tr_step<T, 8, 32>(v, lane);
-    tr_step<T, 4, 16>(v, lane);
-    tr_step<T, 2, 8>(v, lane);
-    tr_step<T, 1, 4>(v, lane);
-    v[0].re += __shfl_xor(v[0].re, 2, 64);
-    v[0].im += __shfl_xor(v[0].im, 2, 64);
-    v[0].re += __shfl_xor(v[0].re, 1, 64);
-    v[0].im += __shfl_xor(v[0].im, 1, 64);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        swap32(v[i].re, v[i + 8].re);
+        swap32(v[i].im, v[i + 8].im);
+        v[i] = v[i] + v[i + 8];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        swap16(v[i].re, v[i + 4].re);
+        swap16(v[i].im, v[i + 4].im);
+        v[i] = v[i] + v[i + 4];
+    }
+    const bool h8 = (lane & 8) != 0, h4 = (lane & 4) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const cx<T> send = h8 ? v[i] : v[i + 2];
+        const cx<T> keep = h8 ? v[i + 2] : v[i];
+        v[i] = keep + dpp<kDppXor8>(send);
+    }
+    {
+        const cx<T> send = h4 ? v[0] : v[1];
+        const cx<T> keep = h4 ? v[1] : v[0];
+        v[0] = keep + dpp<kDppHalfMirror>(send);
+    }
+    v[0] = v[0] + dpp<kDppXor1>(v[0]);
+    v[0] = v[0] + dpp<kDppXor2>(v[0]);
 }
 
 // Table index of the twiddle of slot r in lag block tb, e^(-2 pi i j t / N0)
@@ -134,9 +191,10 @@ __device__ __forceinline__ int lag_twiddle_index(int n0, int j, int tb, int r) {
 }
 
 // NB > 0: the Omega lags span NB blocks of 16 and the thread's 16 NB
-// twiddle-table indices are formed once and kept in registers (Theta's lags
-// lie in the same range at the same slot residues, so they select from
-// them); NB = 0: indices are formed per product and block.
+// twiddles (FP32) or twiddle-table indices (FP64) are formed once and kept in
+// registers (Theta's lags lie in the same range at the same slot residues,
+// so they select from them); NB = 0: indices are formed per product and
+// block.
 template <typename T, int NB>
 __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, int ir_only,
                                                            int sslot, int pchunk,
@@ -164,8 +222,17 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
 #pragma unroll
         for (int q = 0; q < 16; ++q) a[q] = A[(size_t)q * tl];
     }
-    int twi[NB > 0 ? NB : 1][16];
-    if constexpr (NB > 0) {
+    // FP32: the conjugated twiddles of the NB Omega blocks stay in registers
+    // (one workgroup per CU leaves room); FP64: their table indices do.
+    constexpr bool kTwReg = NB > 0 && sizeof(T) == 4;
+    int twi[(NB > 0 && !kTwReg) ? NB : 1][16];
+    cx<T> twv[kTwReg ? NB : 1][16];
+    if constexpr (kTwReg) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) twv[b][r] = cconj(tw[lag_twiddle_index(n0, j, -KO + 16 * b, r)]);
+    } else if constexpr (NB > 0) {
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -188,10 +255,44 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
 #pragma unroll
                 for (int q = 0; q < 16; ++q) v[q] = mk(T(0), T(0));
             }
+            if constexpr (kTwReg) {
+                // Omega blocks use their own twiddles; Theta's slots select
+                // the Omega block their lag lies in
+                auto blocks = [&](auto theta_c) {
+                    constexpr bool TH = decltype(theta_c)::value;
+#pragma unroll
+                    for (int blk = 0; blk < NB; ++blk) {
+                        if (16 * blk > 2 * K) break;
+                        cx<T> s[16];
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            cx<T> w = twv[blk][r];
+                            if constexpr (TH) {
+                                const int tb = -K + 16 * blk, mres = tb & 15;
+                                const int t = tb - mres + r + (r < mres ? 16 : 0);
+                                const int ob = (t + KO) >> 4;
+                                w = twv[0][r];
+#pragma unroll
+                                for (int b = 1; b < NB; ++b)
+                                    if (b == ob) w = twv[b][r];
+                            }
+                            s[r] = cmul(v[r], w);
+                        }
+                        wave_transpose_sum16(s, lane);
+                        if ((lane & 3) == 0)
+                            red[(((size_t)(kk - k0) * nblk + blk) * nwv + wv) * 16 + ((lane >> 2) & 15)] = s[0];
+                    }
+                };
+                if (theta)
+                    blocks(std::true_type{});
+                else
+                    blocks(std::false_type{});
+                continue;
+            }
             for (int blk = 0; 16 * blk <= 2 * K; ++blk) {
                 const int tb = -K + 16 * blk;
                 cx<T> s[16];
-                if constexpr (NB > 0) {
+                if constexpr (NB > 0 && !kTwReg) {
                     // Omega: block blk; Theta: slot r's lag t lies in Omega
                     // block (t + KO) / 16 at the same slot
                     const int mres = tb & 15;
