@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace sfft {
 
 // Complex number in a given real type, stored as (re, im) and aligned so a
@@ -34,6 +36,19 @@ template <typename T>
 __host__ __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
 
 // Maximum number of radix passes of one line transform.
+// a * b + c with one rounding, in the operands' precision.
+__host__ __device__ __forceinline__ float fmat(float a, float b, float c) { return fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fmat(double a, double b, double c) { return fma(a, b, c); }
+
+// f(std::integral_constant<int, I>{}) for I = B .. E - 1, in order.
+template <int B, int E, typename F>
+__host__ __device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 constexpr int kMaxPass = 8;
 constexpr int kMaxDegree = 4;   // largest DK and DB
 // Elements of one line held by one thread during a transform.

@@ -276,9 +276,10 @@ __global__ void __launch_bounds__(256) stencil_reg_kernel(Geom g, const cx<T>* _
 #pragma unroll
     for (int o = 0; o < NO; ++o)
         acc[o] = x0b + o < n0 ? Z[(size_t)zs * plane + (size_t)(x0b + o) * g.hp + m] : mk(T(0), T(0));
+    // Horner over the full degree DK with the stamp terms i > DK - j set to
+    // zero once per tap (no per-output selects).
 #pragma unroll 1
     for (int j = 0; j <= DK; ++j) {
-        constexpr int kMaxI = DK;
         const cx<T>* Zj = Z + (size_t)j * plane + m;
         cx<T> z[NS];
 #pragma unroll
@@ -286,19 +287,25 @@ __global__ void __launch_bounds__(256) stencil_reg_kernel(Geom g, const cx<T>* _
         const int ni = DK - j;
 #pragma unroll
         for (int a = 0; a < L0; ++a) {   // tap a0 = a - W0
-            cx<T> kt[kMaxI + 1];
+            cx<T> kt[DK + 1];
 #pragma unroll
-            for (int i = 0; i <= kMaxI; ++i)
-                if (i <= ni) kt[i] = ktl[term_index(DK, i, j) * L0 + a][mc];
+            for (int i = 0; i <= DK; ++i) {
+                const cx<T> v = ktl[term_index(DK, i <= ni ? i : 0, j) * L0 + a][mc];
+                kt[i] = i <= ni ? v : mk(T(0), T(0));
+            }
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
                 const int s = o + 2 * W0 - a;   // source row x0 - a0
                 const T c = cs[s];
-                cx<T> poly = kt[ni];
+                cx<T> poly = kt[DK];
 #pragma unroll
-                for (int i = kMaxI - 1; i >= 0; --i)
-                    if (i < ni) poly = mk(poly.re * c + kt[i].re, poly.im * c + kt[i].im);
-                acc[o] = acc[o] - cmul(poly, z[s]);
+                for (int i = DK - 1; i >= 0; --i)
+                    poly = mk(fmat(poly.re, c, kt[i].re), fmat(poly.im, c, kt[i].im));
+                // the tap's term first, so that each tap rounds once at the
+                // accumulator's magnitude (|Z_S|, far above the result)
+                const cx<T> t = mk(fmat(poly.re, z[s].re, -poly.im * z[s].im),
+                                   fmat(poly.re, z[s].im, poly.im * z[s].re));
+                acc[o] = acc[o] - t;
             }
             __builtin_amdgcn_sched_barrier(0);
         }
