@@ -36,6 +36,20 @@ template <typename T>
 __host__ __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
 
 // Maximum number of radix passes of one line transform.
+// Zero, hidden from the optimiser. Inside a loop, p + opaque_zero() keeps
+// the addresses derived from p from being formed once before the loop and
+// held in registers across every iteration (p keeps its address space).
+__device__ __forceinline__ int opaque_zero() {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return z;
+}
+
+// A wave-uniform value moved to a scalar register (lane 0's copy).
+__device__ __forceinline__ float uniform(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
 // a * b + c with one rounding, in the operands' precision.
 __host__ __device__ __forceinline__ float fmat(float a, float b, float c) { return fmaf(a, b, c); }
 __host__ __device__ __forceinline__ double fmat(double a, double b, double c) { return fma(a, b, c); }

@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
                                                       cx<T>* __restrict__ Z,
                                                       const cx<T>* __restrict__ twt) {
     cx<T>* lds = lds_base<T>();
-    const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
+    const int line = threadIdx.x / lp.tl, lt0 = threadIdx.x - line * lp.tl;
     const int row = blockIdx.x * lp.lpw + line;
     const bool act = row < g.n0;
     const int n1 = g.n1;
@@ -36,6 +36,9 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
     for (int pk = 0; pk < npk; ++pk) {
         const int ia = 2 * pk, ib = 2 * pk + 1;
         const bool hasb = ib < src.n;
+        // the thread index through an opaque zero: addresses are formed per
+        // packed pair instead of held in registers across the loop
+        const int lt = lt0 + opaque_zero();
         cx<T> v[kElemsPerThread];
         if (act) {
             const Tin* pa = (src.img[ia] ? img1 : img0) + (size_t)row * n1;
@@ -95,26 +98,45 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
     const int n0 = g.n0;
     const int a = jobs.arr[job];
     cx<T>* buf = lds + line * line_lds_elems(lp.n);
-    cx<T> z[kElemsPerThread];
-    if (act) {
-        const cx<T>* zc = Z + (size_t)a * n0 * g.hp + m;
+    // FP32 holds the column across the weights (z = c0^i Z_a); FP64 reads
+    // it again per weight (from L2 after the first) to stay clear of spills
+    constexpr bool kHold = sizeof(T) == 4;
+    const cx<T>* zc = Z + (size_t)a * n0 * g.hp + m;
+    cx<T> z[kHold ? kElemsPerThread : 1];
+    if constexpr (kHold) {
+        if (act) {
 #pragma unroll
-        for (int e = 0; e < kElemsPerThread; ++e) z[e] = zc[(size_t)(lt + e * lp.tl) * g.hp];
+            for (int e = 0; e < kElemsPerThread; ++e) z[e] = zc[(size_t)(lt + e * lp.tl) * g.hp];
+        }
     }
     const int nw = jobs.nw[job];
+    T c0[kElemsPerThread];
+#pragma unroll
+    for (int e = 0; e < kElemsPerThread; ++e) c0[e] = coord<T>(lt + e * lp.tl, n0);
 #pragma unroll 1
     for (int i = 0; i < nw; ++i) {
+        // the thread index through an opaque zero: addresses are formed per
+        // weight instead of held in registers across the loop
+        const int li = lt + opaque_zero();
         cx<T> v[kElemsPerThread];
+        if constexpr (kHold) {
+            if (i > 0) {
 #pragma unroll
-        for (int e = 0; e < kElemsPerThread; ++e) {
-            const int x0 = lt + e * lp.tl;
-            v[e] = act ? cscale(z[e], ipow(coord<T>(x0, n0), i)) : mk(T(0), T(0));
+                for (int e = 0; e < kElemsPerThread; ++e) z[e] = cscale(z[e], c0[e]);
+            }
+#pragma unroll
+            for (int e = 0; e < kElemsPerThread; ++e) v[e] = act ? z[e] : mk(T(0), T(0));
+        } else {
+#pragma unroll
+            for (int e = 0; e < kElemsPerThread; ++e)
+                v[e] = act ? cscale(zc[(size_t)(li + e * lp.tl) * g.hp], ipow(c0[e], i))
+                           : mk(T(0), T(0));
         }
-        line_fft<-1, T, PL>(v, buf, lp, lt, twt);
+        line_fft<-1, T, PL>(v, buf, lp, li, twt);
         if (act) {
             cx<T>* xo = X + ((size_t)jobs.spec[job][i] * g.h + m) * n0;
 #pragma unroll
-            for (int e = 0; e < kElemsPerThread; ++e) xo[lt + e * lp.tl] = v[e];
+            for (int e = 0; e < kElemsPerThread; ++e) xo[li + e * lp.tl] = v[e];
         }
     }
 }

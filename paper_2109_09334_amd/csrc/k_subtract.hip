@@ -257,7 +257,9 @@ __global__ void __launch_bounds__(256) stencil_reg_kernel(Geom g, const cx<T>* _
     __shared__ cx<T> ktl[P * L0][64];
     const int mc = threadIdx.x & 63;
     const int m = blockIdx.x * 64 + mc;
-    const int x0b = (blockIdx.y * 4 + (threadIdx.x >> 6)) * NO;
+    // one wave per row group: x0b, the source rows and their coordinates are
+    // wave-uniform and kept in scalar registers
+    const int x0b = __builtin_amdgcn_readfirstlane((blockIdx.y * 4 + (threadIdx.x >> 6)) * NO);
     const int n0 = g.n0;
     const bool mok = m < g.h;
     for (int t = threadIdx.x >> 6; t < P * L0; t += 4)
@@ -270,7 +272,7 @@ __global__ void __launch_bounds__(256) stencil_reg_kernel(Geom g, const cx<T>* _
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         xs[s] = imod(x0b - W0 + s, n0);
-        cs[s] = coord<T>(xs[s], n0);
+        cs[s] = uniform(coord<T>(xs[s], n0));
     }
     cx<T> acc[NO];
 #pragma unroll
@@ -281,9 +283,12 @@ __global__ void __launch_bounds__(256) stencil_reg_kernel(Geom g, const cx<T>* _
 #pragma unroll 1
     for (int j = 0; j <= DK; ++j) {
         const cx<T>* Zj = Z + (size_t)j * plane + m;
+        // row offsets formed per j (an opaque zero keeps them out of the
+        // registers held across the loop)
+        const int oz = opaque_zero();
         cx<T> z[NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) z[s] = Zj[(size_t)xs[s] * g.hp];
+        for (int s = 0; s < NS; ++s) z[s] = Zj[(size_t)(xs[s] + oz) * g.hp];
         const int ni = DK - j;
 #pragma unroll
         for (int a = 0; a < L0; ++a) {   // tap a0 = a - W0
