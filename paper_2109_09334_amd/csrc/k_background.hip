@@ -94,8 +94,8 @@ __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, const Tin* __restr
         for (int r = 0; r <= jb; ++r) v += binom(jb, r) * ipow(sh, jb - r) * mom[wv][ja + r];
         const int lo = d1 > 0 ? n1 - d1 : 0, hi = d1 > 0 ? n1 : -d1;
         for (int x1 = lo; x1 < hi; ++x1) {
-            const double c = coord<double>(x1, n1);
-            const double tor = coord<double>(imod(x1 + d1, n1), n1);
+            const double c = (double)(2 * x1 - (n1 - 1)) * rn;
+            const double tor = (double)(2 * imod(x1 + d1, n1) - (n1 - 1)) * rn;
             v += (double)row[x1] * ipow(c, ja) * (ipow(tor, jb) - ipow(c + sh, jb));
         }
         vrow[(size_t)x0 * na * nb * nd + idx] = v;
@@ -114,12 +114,13 @@ __global__ void __launch_bounds__(256) polymom_kernel(Geom g, const double* __re
                                                        int nitem, int ne,
                                                        double* __restrict__ part) {
     const int x0a = blockIdx.x * kPolyRowChunk, x0b = min(g.n0, x0a + kPolyRowChunk);
+    const double rn = 1.0 / (double)(g.n0 - 1);
     for (int item = threadIdx.x; item < nitem; item += blockDim.x) {
         double m[kMaxMom];
 #pragma unroll
         for (int e = 0; e < kMaxMom; ++e) m[e] = 0.0;
         for (int x0 = x0a; x0 < x0b; ++x0) {
-            const double c = coord<double>(x0, g.n0);
+            const double c = (double)(2 * x0 - (g.n0 - 1)) * rn;
             double pw = vrow[(size_t)x0 * nitem + item];
 #pragma unroll
             for (int e = 0; e < kMaxMom; ++e) {
@@ -167,14 +168,15 @@ __global__ void __launch_bounds__(256) polycorr_kernel(Geom g, const double* __r
     const int nb = dbb + 1;
     const int nitem = (da + 1) * nb * nd1;
     const int item = (ja * nb + jb) * nd1 + d1;
-    const double sh = 2.0 * (double)d0 / (double)(n0 - 1);
+    const double rn = 1.0 / (double)(n0 - 1);
+    const double sh = 2.0 * (double)d0 * rn;
     double v = 0.0;
     for (int r = 0; r <= ib; ++r)
         v += binom(ib, r) * ipow(sh, ib - r) * mom[(size_t)(ia + r) * nitem + item];
     const int lo = d0 > 0 ? n0 - d0 : 0, hi = d0 > 0 ? n0 : -d0;
     for (int x0 = lo; x0 < hi; ++x0) {
-        const double c = coord<double>(x0, n0);
-        const double tor = coord<double>(imod(x0 + d0, n0), n0);
+        const double c = (double)(2 * x0 - (n0 - 1)) * rn;
+        const double tor = (double)(2 * imod(x0 + d0, n0) - (n0 - 1)) * rn;
         v += vrow[(size_t)x0 * nitem + item] * ipow(c, ia) * (ipow(tor, ib) - ipow(c + sh, ib));
     }
     pi[idx] = v;
@@ -210,10 +212,12 @@ __global__ void __launch_bounds__(256) polysum_kernel(Geom g, int dmax, double* 
         e = b % (2 * dmax + 1);
     }
     const int n = axis ? g.n1 : g.n0;
+    const double rn = 1.0 / (double)(n - 1);
     double acc = 0.0;
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
-        const double c = coord<double>(x, n);
-        acc += power ? ipow(c, e) : ipow(coord<double>(imod(x - d, n), n), ab) * ipow(c, a);
+        const double c = (double)(2 * x - (n - 1)) * rn;
+        const double cs = (double)(2 * imod(x - d, n) - (n - 1)) * rn;
+        acc += power ? ipow(c, e) : ipow(cs, ab) * ipow(c, a);
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;

@@ -208,9 +208,14 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
     const int line = threadIdx.x / tl, j = threadIdx.x - line * tl;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
     const int nwl = tl >> 6;                    // waves per line
+    // ir_only: one block per column block holds the spectrum in slot sslot
+    // and forms conj(X_k) X_sslot for every kernel term k (Theta products
+    // only); otherwise block (column block, kb) holds X_kb and forms its
+    // Omega products with k >= kb and its Theta product.
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int jx = slot / g.P;
-    const int kb = slot - jx * g.P;
+    const int nkb = ir_only ? 1 : g.P;
+    const int jx = slot / nkb;
+    const int kb = slot - jx * nkb;
     const int cb = 8 * jx + xcd;
     const int m = cb * lp.lpw + line;
     const bool act = m < g.h;
@@ -218,7 +223,7 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
     const int KO = 2 * g.w0, nblk = (2 * KO + 16) / 16;   // lag blocks of Omega (Theta uses fewer)
     cx<T> a[16];
     if (act) {
-        const cx<T>* A = X + ((size_t)kb * g.h + m) * n0 + j;
+        const cx<T>* A = X + ((size_t)(ir_only ? sslot : kb) * g.h + m) * n0 + j;
 #pragma unroll
         for (int q = 0; q < 16; ++q) a[q] = A[(size_t)q * tl];
     }
@@ -238,18 +243,23 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
 #pragma unroll
             for (int r = 0; r < 16; ++r) twi[b][r] = lag_twiddle_index(n0, j, -KO + 16 * b, r);
     }
-    const int kfirst = ir_only ? g.P : kb;
-    for (int k0 = kfirst; k0 <= g.P; k0 += pchunk) {
-        const int k1 = min(g.P + 1, k0 + pchunk);
+    const int kbeg = ir_only ? 0 : kb, kend = ir_only ? g.P : g.P + 1;
+    for (int k0 = kbeg; k0 < kend; k0 += pchunk) {
+        const int k1 = min(kend, k0 + pchunk);
         for (int kk = k0; kk < k1; ++kk) {
-            const bool theta = kk == g.P;
-            const int k = theta ? sslot : kk;
+            const bool theta = ir_only || kk == g.P;
+            const int k = ir_only ? kk : (theta ? sslot : kk);
             const int K = theta ? g.w0 : KO;
             cx<T> v[16];
             if (act) {
                 const cx<T>* B = X + ((size_t)k * g.h + m) * n0 + j;
+                if (ir_only) {
 #pragma unroll
-                for (int q = 0; q < 16; ++q) v[q] = cmulc(a[q], B[(size_t)q * tl]);
+                    for (int q = 0; q < 16; ++q) v[q] = cmulc(B[(size_t)q * tl], a[q]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) v[q] = cmulc(a[q], B[(size_t)q * tl]);
+                }
                 Dft<16, 1, T>::run(v);
             } else {
 #pragma unroll
@@ -322,7 +332,7 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
         for (int o = j; o < nout; o += tl) {
             const int r = o & 15, blk = (o >> 4) % nblk, ip = (o >> 4) / nblk;
             const int kk = k0 + ip;
-            const bool theta = kk == g.P;
+            const bool theta = ir_only || kk == g.P;
             const int K = theta ? g.w0 : KO;
             const int tb = -K + 16 * blk;
             const int t = tb + ((r - tb) & 15);
@@ -330,7 +340,8 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
             cx<T> tot = red[(((size_t)ip * nblk + blk) * nwv + line * nwl) * 16 + r];
             for (int w = 1; w < nwl; ++w)
                 tot = tot + red[(((size_t)ip * nblk + blk) * nwv + line * nwl + w) * 16 + r];
-            const int p = theta ? g.npair + kb : kb * g.P - kb * (kb - 1) / 2 + (kk - kb);
+            const int p = theta ? g.npair + (ir_only ? kk : kb)
+                                : kb * g.P - kb * (kb - 1) / 2 + (kk - kb);
             Cl[((size_t)p * g.D0 + t + 2 * g.w0) * g.hp + m] = tot;
         }
         __syncthreads();
@@ -427,10 +438,11 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
         const int nblk = (4 * g.w0 + 16) / 16;
         const size_t per = (size_t)nblk * nwv * 16 * sizeof(cx<T>);
         const int pchunk = (int)std::max<size_t>(1, std::min<size_t>(g.P + 1, 32768 / per));
-        dim3 grid((ncb + 7) / 8 * 8 * g.P);
+        const bool ir_only = p0 != 0;
+        dim3 grid((ncb + 7) / 8 * 8 * (ir_only ? 1 : g.P));
         auto k = nblk == 1 ? lagcol_tail_kernel<T, 1>
                  : nblk == 2 ? lagcol_tail_kernel<T, 2> : lagcol_tail_kernel<T, 0>;
-        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), pchunk * per, st, g, lp, p0 == 0 ? 0 : 1,
+        hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), pchunk * per, st, g, lp, ir_only ? 1 : 0,
                            sslot, pchunk, X, Cl, tw);
         return hipGetLastError();
     }
