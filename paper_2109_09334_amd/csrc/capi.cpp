@@ -228,6 +228,12 @@ int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out)
     char* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess) return SFFT_E_NOMEM;
     carve(pl->ws, pl->g, mixed ? 8 : 16, mixed ? 4 : 8, base);
+    // The status flag starts clear: the allocation may hold a freed
+    // workspace's bytes, and the flag is read for every plan at a sync.
+    if (hipMemset(pl->ws.flag, 0, sizeof(int)) != hipSuccess) {
+        (void)hipFree(base);
+        return SFFT_E_HIP;
+    }
     pl->ws.base = base;
     pl->ws.bytes = bytes;
     ctx->used += bytes;
@@ -237,6 +243,8 @@ int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out)
 
 void destroy_plan(sfft_ctx* ctx, std::unique_ptr<Plan>& pl) {
     if (!pl) return;
+    for (auto& gx : pl->graph)
+        if (gx) (void)hipGraphExecDestroy(gx);
     if (pl->ws.base) (void)hipFree(pl->ws.base);
     ctx->used -= pl->ws.bytes;
     pl.reset();
@@ -283,7 +291,7 @@ static RowSources pair_sources(const Geom& g, bool pedestal) {
 // Stage 1 of the build, FP64: polynomial-correlation tables of R (|d| <= 2w)
 // and S (|d| <= w), 1-D polynomial sums, and the pedestals (image means).
 template <typename Tin>
-static hipError_t poly_tables(Plan& pl, const Tin* r, const Tin* s, hipStream_t st) {
+static hipError_t poly_tables(Plan& pl, IoRef<const Tin> r, IoRef<const Tin> s, hipStream_t st) {
     const Geom& g = pl.g;
     Workspace& w = pl.ws;
     const int dm = poly_degree(g);
@@ -299,7 +307,7 @@ static hipError_t poly_tables(Plan& pl, const Tin* r, const Tin* s, hipStream_t 
 
 // Row and column transforms of the pedestal-free fit pair: Z[0..nr), X[0..P].
 template <typename T, typename Tin>
-static hipError_t forward_fit(Plan& pl, const Tin* r, const Tin* s, hipStream_t st) {
+static hipError_t forward_fit(Plan& pl, IoRef<const Tin> r, IoRef<const Tin> s, hipStream_t st) {
     const Geom& g = pl.g;
     Workspace& w = pl.ws;
     hipError_t e;
@@ -326,7 +334,7 @@ static hipError_t forward_fit(Plan& pl, const Tin* r, const Tin* s, hipStream_t 
 // Pedestal tables, transforms, products and pruned inverses, then the exact
 // FP64 pedestal corrections: Omega, Theta, Lambda, C, E of the fit pair.
 template <typename T, typename Tin>
-static hipError_t lag_tables(Plan& pl, const Tin* r, const Tin* s, hipStream_t st) {
+static hipError_t lag_tables(Plan& pl, IoRef<const Tin> r, IoRef<const Tin> s, hipStream_t st) {
     const Geom& g = pl.g;
     Workspace& w = pl.ws;
     hipError_t e = poly_tables<Tin>(pl, r, s, st);
@@ -348,7 +356,8 @@ static hipError_t lag_tables(Plan& pl, const Tin* r, const Tin* s, hipStream_t s
 }
 
 template <typename T, typename Tin>
-static hipError_t build(Plan& pl, const Tin* r, const Tin* s, double* G, double* h, hipStream_t st) {
+static hipError_t build(Plan& pl, IoRef<const Tin> r, IoRef<const Tin> s, double* G, double* h,
+                        hipStream_t st) {
     hipError_t e = lag_tables<T, Tin>(pl, r, s, st);
     Workspace& w = pl.ws;
     StageTimer t_(pl.prof, "gather", st);
@@ -361,7 +370,7 @@ static hipError_t build(Plan& pl, const Tin* r, const Tin* s, double* G, double*
 // (pedestals in w.ped) and the pedestal terms re-enter in FP64 through the
 // sky table together with the background.
 template <typename T, typename Tout>
-static hipError_t difference(Plan& pl, int zs, bool pedestal, const double* coef, Tout* d,
+static hipError_t difference(Plan& pl, int zs, bool pedestal, const double* coef, IoRef<Tout> d,
                              hipStream_t st) {
     const Geom& g = pl.g;
     Workspace& w = pl.ws;
@@ -469,38 +478,69 @@ static int run_solve_t(Plan& pl, const double* G, const double* h, const void* r
 }
 
 template <typename T, typename Tin>
-static int run_subtract_t(Plan& pl, const void* r, const void* s, const double* coef, void* d,
-                          hipStream_t st) {
+static hipError_t subtract_path(Plan& pl, IoRef<const Tin> r, IoRef<const Tin> s,
+                                const double* coef, IoRef<Tin> d, hipStream_t st) {
     const Geom& g = pl.g;
     hipError_t e;
     {
         StageTimer t_(pl.prof, "rowfwd", st);
-        e = launch_rowfwd<T, Tin>(g, pl.lp1, pair_sources(g, false), (const Tin*)r, (const Tin*)s,
-                                  nullptr, cxp<T>(pl.ws.Z), cxp<T>(pl.t1.twt), st);
+        e = launch_rowfwd<T, Tin>(g, pl.lp1, pair_sources(g, false), r, s, nullptr,
+                                  cxp<T>(pl.ws.Z), cxp<T>(pl.t1.twt), st);
     }
-    if (!e) e = difference<T, Tin>(pl, g.dk + 1, false, coef, (Tin*)d, st);
-    return hip_status(e);
+    if (!e) e = difference<T, Tin>(pl, g.dk + 1, false, coef, d, st);
+    return e;
+}
+
+template <typename T, typename Tin>
+static int run_subtract_t(Plan& pl, const void* r, const void* s, const double* coef, void* d,
+                          hipStream_t st) {
+    return hip_status(subtract_path<T, Tin>(pl, (const Tin*)r, (const Tin*)s, coef, (Tin*)d, st));
+}
+
+// The whole path of one request. same_pair: the apply pair is the fit pair,
+// whose pedestal-free transforms are reused for D.
+template <typename T, typename Tin>
+static hipError_t all_path(Plan& pl, IoRef<const Tin> rf, IoRef<const Tin> sf, IoRef<const Tin> r,
+                           IoRef<const Tin> s, IoRef<double> coef, IoRef<Tin> d, bool same_pair,
+                           hipStream_t st) {
+    Workspace& w = pl.ws;
+    hipError_t e = launch_clear_flag(w.flag, st);
+    if (!e) e = build<T, Tin>(pl, rf, sf, w.G, w.h, st);
+    if (!e) e = factor_solve(pl, w.G, w.h, w.coef, st);
+    for (int it = 0; !e && pl.p.precision == SFFT_MIXED && it < refine_steps(); ++it)
+        e = refine<T>(pl, w.coef, st);
+    if (!e) e = launch_copy_f64(coef, w.coef, pl.g.nu, st);
+    if (e) return e;
+    if (same_pair) return difference<T, Tin>(pl, pl.g.dk + 1, true, w.coef, d, st);
+    return subtract_path<T, Tin>(pl, r, s, w.coef, d, st);
 }
 
 template <typename T, typename Tin>
 static int run_all_t(Plan& pl, const void* rf, const void* sf, const void* r, const void* s,
                      double* coef, void* d, hipStream_t st) {
-    Workspace& w = pl.ws;
-    hipError_t e = launch_clear_flag(w.flag, st);
-    if (!e) e = build<T, Tin>(pl, (const Tin*)rf, (const Tin*)sf, w.G, w.h, st);
-    if (!e) e = factor_solve(pl, w.G, w.h, w.coef, st);
-    for (int it = 0; !e && pl.p.precision == SFFT_MIXED && it < refine_steps(); ++it)
-        e = refine<T>(pl, w.coef, st);
+    return hip_status(all_path<T, Tin>(pl, (const Tin*)rf, (const Tin*)sf, (const Tin*)r,
+                                       (const Tin*)s, coef, (Tin*)d, r == rf && s == sf, st));
+}
+
+// Capture of all_path with every caller buffer read from the plan's I/O
+// table (the kernels' arguments are fixed at capture).
+template <typename T, typename Tin>
+static int capture_all_t(Plan& pl, bool same_pair, hipStream_t st, hipGraphExec_t* out) {
+    void* const* io = pl.ws.io;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
     if (e) return hip_status(e);
-    if (coef) {
-        e = hipMemcpyAsync(coef, w.coef, pl.g.nu * sizeof(double), hipMemcpyDeviceToDevice, st);
-        if (e) return hip_status(e);
+    const hipError_t ek = all_path<T, Tin>(
+        pl, IoRef<const Tin>(io, kIoRfit), IoRef<const Tin>(io, kIoSfit), IoRef<const Tin>(io, kIoR),
+        IoRef<const Tin>(io, kIoS), IoRef<double>(io, kIoCoef), IoRef<Tin>(io, kIoD), same_pair, st);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(st, &graph);
+    if (ek || e) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_status(ek ? ek : e);
     }
-    if (r == rf && s == sf) {
-        e = difference<T, Tin>(pl, pl.g.dk + 1, true, w.coef, (Tin*)d, st);
-        return hip_status(e);
-    }
-    return run_subtract_t<T, Tin>(pl, r, s, w.coef, d, st);
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return hip_status(e);
 }
 
 // Dispatch on (compute type, image type).
@@ -514,6 +554,25 @@ static int run_all_t(Plan& pl, const void* rf, const void* sf, const void* r, co
 int plan_run(Plan& pl, const void* rf, const void* sf, const void* r, const void* s, double* coef,
              void* d, hipStream_t st) {
     return SFFT_DISPATCH(pl, run_all_t, rf, sf, r, s, coef, d, st);
+}
+
+int plan_run_graph(Plan& pl, const void* rf, const void* sf, const void* r, const void* s,
+                   double* coef, void* d, hipStream_t st) {
+    const bool same_pair = r == rf && s == sf;
+    hipGraphExec_t& gx = pl.graph[same_pair ? 0 : 1];
+    if (!gx) {
+        Profiler* saved = pl.prof;
+        pl.prof = nullptr;   // no timing events inside a graph
+        const int rc = SFFT_DISPATCH(pl, capture_all_t, same_pair, st, &gx);
+        pl.prof = saved;
+        if (rc) {
+            gx = nullptr;
+            return rc;
+        }
+    }
+    hipError_t e = launch_set_io(pl.ws.io, rf, sf, r, s, coef, d, st);
+    if (!e) e = hipGraphLaunch(gx, st);
+    return hip_status(e);
 }
 
 int plan_read_flag(Plan& pl, hipStream_t st, int* flag) {

@@ -45,6 +45,24 @@ __device__ __forceinline__ int opaque_zero() {
     return z;
 }
 
+// Address of a caller-owned buffer as a kernel sees it: the argument p, or,
+// when tab is set, entry `slot` of a device table that is written before
+// each launch (a captured graph fixes its kernel arguments, the table keeps
+// the caller's buffers free to change between replays).
+template <typename T>
+struct IoRef {
+    T* p = nullptr;
+    void* const* tab = nullptr;
+    int slot = 0;
+    IoRef() = default;
+    __host__ __device__ IoRef(T* ptr) : p(ptr) {}
+    __host__ __device__ IoRef(void* const* t, int s) : tab(t), slot(s) {}
+    __device__ __forceinline__ T* get() const { return tab ? static_cast<T*>(tab[slot]) : p; }
+};
+
+// Slots of a request's caller buffers in the I/O table.
+constexpr int kIoRfit = 0, kIoSfit = 1, kIoR = 2, kIoS = 3, kIoCoef = 4, kIoD = 5, kIoSlots = 8;
+
 // A wave-uniform value moved to a scalar register (lane 0's copy).
 __device__ __forceinline__ float uniform(float x) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));

@@ -2,12 +2,14 @@
 #include "engine.hpp"
 
 #include <chrono>
+#include <cstdlib>
 
 namespace sfft {
 
 int read_plan_flag(Plan& pl, int* flag);
 
-Engine::Engine(sfft_ctx* ctx, int slots) : ctx_(ctx), slots_(slots > 0 ? slots : 4) {
+Engine::Engine(sfft_ctx* ctx, int slots)
+    : ctx_(ctx), slots_(slots > 0 ? slots : 4), graphs_(getenv("SFFT_ENGINE_DIRECT") == nullptr) {
     (void)hipSetDevice(ctx_->device);
     for (auto& s : slots_) {
         (void)hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking);
@@ -132,8 +134,10 @@ void Engine::loop() {
                 continue;
             }
             pl->p.dtype = j.req.p.dtype;
-            rc = plan_run(*pl, j.req.r_fit, j.req.s_fit, j.req.r, j.req.s, j.req.coef, j.req.d,
-                          free_slot->st);
+            rc = graphs_ ? plan_run_graph(*pl, j.req.r_fit, j.req.s_fit, j.req.r, j.req.s,
+                                          j.req.coef, j.req.d, free_slot->st)
+                         : plan_run(*pl, j.req.r_fit, j.req.s_fit, j.req.r, j.req.s, j.req.coef,
+                                    j.req.d, free_slot->st);
             if (!rc && hipEventRecord(free_slot->ev, free_slot->st) != hipSuccess) rc = SFFT_E_HIP;
             if (rc) {
                 status_[j.ticket] = rc;

@@ -4,7 +4,10 @@
 // the queue as soon as a slot (a HIP stream) is free and a workspace for
 // its geometry fits the context's HBM budget -- reusing an idle workspace of
 // the same geometry, or evicting idle workspaces of other geometries -- and
-// enqueues the whole hot path on the slot's stream. Admitted requests run
+// enqueues the whole hot path on the slot's stream: the path is captured
+// once per workspace into a HIP graph that reads the request's buffers from
+// a device table, so a request costs a table write and a graph launch
+// instead of some seventy kernel launches. Admitted requests run
 // concurrently on the device; completion is detected with an event per
 // slot. Each request's arithmetic is independent of the others (no shared
 // buffers, no atomics across requests), so its result is the same alone or
@@ -49,6 +52,7 @@ private:
 
     sfft_ctx* ctx_;
     std::vector<Slot> slots_;
+    bool graphs_;   // replay each workspace's captured graph (SFFT_ENGINE_DIRECT: launch directly)
     std::deque<Job> queue_;
     std::map<uint64_t, int> status_;
     std::multimap<PlanKey, std::unique_ptr<Plan>> idle_;

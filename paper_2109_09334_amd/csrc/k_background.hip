@@ -52,8 +52,9 @@ __device__ __forceinline__ void block_sum_bg(double* v, double* red) {
 // are wave sums (every lane ends with all of them); the wrapped-column
 // corrections read the row again (L1).
 template <typename Tin, int NE>
-__global__ void __launch_bounds__(256) polyrow_kernel(Geom g, const Tin* __restrict__ img, int da,
+__global__ void __launch_bounds__(256) polyrow_kernel(Geom g, IoRef<const Tin> imgr, int da,
                                                       int dbb, int K1, double* __restrict__ vrow) {
+    const Tin* __restrict__ img = imgr.get();
     __shared__ double mom[4][kMaxMom];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int x0 = blockIdx.x * 4 + wv;
@@ -332,8 +333,8 @@ __global__ void __launch_bounds__(256) lagfix_kernel(Geom g, int mode, const dou
 }
 
 template <typename Tin>
-hipError_t launch_polyrow(const Geom& g, const Tin* img, int da, int dbb, int K1, double* vrow,
-                          hipStream_t st) {
+hipError_t launch_polyrow(const Geom& g, IoRef<const Tin> img, int da, int dbb, int K1,
+                          double* vrow, hipStream_t st) {
     const dim3 grid((g.n0 + 3) / 4), block(256);
     switch (da + dbb + 1) {
 #define SFFT_POLYROW(NE)                                                                        \
@@ -398,9 +399,9 @@ hipError_t launch_lagfix(const Geom& g, int mode, const double* ped, const doubl
     return hipGetLastError();
 }
 
-template hipError_t launch_polyrow<float>(const Geom&, const float*, int, int, int, double*,
+template hipError_t launch_polyrow<float>(const Geom&, IoRef<const float>, int, int, int, double*,
                                           hipStream_t);
-template hipError_t launch_polyrow<double>(const Geom&, const double*, int, int, int, double*,
-                                           hipStream_t);
+template hipError_t launch_polyrow<double>(const Geom&, IoRef<const double>, int, int, int,
+                                           double*, hipStream_t);
 
 }  // namespace sfft

@@ -20,12 +20,14 @@ __device__ __forceinline__ cx<T>* lds_base() {
 
 template <typename T, typename Tin, typename PL>
 __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSources src,
-                                                      const Tin* __restrict__ img0,
-                                                      const Tin* __restrict__ img1,
+                                                      IoRef<const Tin> img0r,
+                                                      IoRef<const Tin> img1r,
                                                       const double* __restrict__ ped,
                                                       cx<T>* __restrict__ Z,
                                                       const cx<T>* __restrict__ twt) {
     cx<T>* lds = lds_base<T>();
+    const Tin* __restrict__ img0 = img0r.get();
+    const Tin* __restrict__ img1 = img1r.get();
     const int line = threadIdx.x / lp.tl, lt0 = threadIdx.x - line * lp.tl;
     const int row = blockIdx.x * lp.lpw + line;
     const bool act = row < g.n0;
@@ -148,9 +150,10 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
 template <typename T, typename Tout, typename PL>
 __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
                                                       const cx<T>* __restrict__ Dt,
-                                                      Tout* __restrict__ d,
+                                                      IoRef<Tout> dr,
                                                       const double* __restrict__ sky,
                                                       const cx<T>* __restrict__ twt) {
+    Tout* __restrict__ d = dr.get();
     cx<T>* lds = lds_base<T>();
     const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
     const int pr = blockIdx.x * lp.lpw + line;
@@ -242,9 +245,9 @@ static hipError_t set_lds(K kern, size_t bytes) {
 }
 
 template <typename T, typename Tin>
-hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& src, const Tin* img0,
-                         const Tin* img1, const double* ped, cx<T>* Z, const cx<T>* twt,
-                         hipStream_t st) {
+hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& src,
+                         IoRef<const Tin> img0, IoRef<const Tin> img1, const double* ped, cx<T>* Z,
+                         const cx<T>* twt, hipStream_t st) {
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     dim3 grid((g.n0 + lp.lpw - 1) / lp.lpw);
     return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
@@ -273,7 +276,7 @@ hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs,
 }
 
 template <typename T, typename Tout>
-hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, Tout* d,
+hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, IoRef<Tout> d,
                          const double* sky, const cx<T>* twt, hipStream_t st) {
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     dim3 grid((g.n0 / 2 + lp.lpw - 1) / lp.lpw);
@@ -309,9 +312,9 @@ SFFT_INST_T(float)
 SFFT_INST_T(double)
 #define SFFT_INST_TT(T, U)                                                                        \
     template hipError_t launch_rowfwd<T, U>(const Geom&, const LinePlan&, const RowSources&,      \
-                                            const U*, const U*, const double*, cx<T>*,            \
-                                            const cx<T>*, hipStream_t);                           \
-    template hipError_t launch_rowinv<T, U>(const Geom&, const LinePlan&, const cx<T>*, U*,       \
+                                            IoRef<const U>, IoRef<const U>, const double*,        \
+                                            cx<T>*, const cx<T>*, hipStream_t);                   \
+    template hipError_t launch_rowinv<T, U>(const Geom&, const LinePlan&, const cx<T>*, IoRef<U>, \
                                             const double*, const cx<T>*, hipStream_t);
 SFFT_INST_TT(float, float)
 SFFT_INST_TT(float, double)

@@ -85,4 +85,35 @@ hipError_t launch_gather(const Geom& g, const double* om, const double* th, cons
     return hipGetLastError();
 }
 
+
+__global__ void set_io_kernel(void** io, const void* rf, const void* sf, const void* r,
+                              const void* s, double* coef, void* d) {
+    io[kIoRfit] = const_cast<void*>(rf);
+    io[kIoSfit] = const_cast<void*>(sf);
+    io[kIoR] = const_cast<void*>(r);
+    io[kIoS] = const_cast<void*>(s);
+    io[kIoCoef] = coef;
+    io[kIoD] = d;
+}
+
+__global__ void __launch_bounds__(256) copy_f64_kernel(IoRef<double> dstr,
+                                                       const double* __restrict__ src, int n) {
+    double* __restrict__ dst = dstr.get();
+    if (!dst) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_set_io(void** io, const void* rf, const void* sf, const void* r, const void* s,
+                         double* coef, void* d, hipStream_t st) {
+    hipLaunchKernelGGL(set_io_kernel, dim3(1), dim3(1), 0, st, io, rf, sf, r, s, coef, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(IoRef<double> dst, const double* src, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_f64_kernel, dim3((n + 255) / 256), dim3(256), 0, st, dst, src, n);
+    return hipGetLastError();
+}
+
 }  // namespace sfft

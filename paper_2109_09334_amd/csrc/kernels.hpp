@@ -29,14 +29,14 @@ struct ColJobs {
 };
 
 template <typename T, typename Tin>
-hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& src, const Tin* img0,
-                         const Tin* img1, const double* ped, cx<T>* Z, const cx<T>* twt,
-                         hipStream_t st);
+hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& src,
+                         IoRef<const Tin> img0, IoRef<const Tin> img1, const double* ped, cx<T>* Z,
+                         const cx<T>* twt, hipStream_t st);
 template <typename T>
 hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs, const cx<T>* Z,
                          cx<T>* X, const cx<T>* twt, hipStream_t st);
 template <typename T, typename Tout>
-hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, Tout* d,
+hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, IoRef<Tout> d,
                          const double* sky, const cx<T>* twt, hipStream_t st);
 template <typename T>
 hipError_t launch_fft_lines(const LinePlan& lp, int nlines, int sign, const cx<T>* in, cx<T>* out,
@@ -56,8 +56,8 @@ hipError_t launch_lagrow(const Geom& g, int p0, int p1, const cx<T>* Cl, const d
 
 // FP64 polynomial-correlation tables and pedestal corrections (k_background).
 template <typename Tin>
-hipError_t launch_polyrow(const Geom& g, const Tin* img, int da, int dbb, int K1, double* vrow,
-                          hipStream_t st);
+hipError_t launch_polyrow(const Geom& g, IoRef<const Tin> img, int da, int dbb, int K1,
+                          double* vrow, hipStream_t st);
 // part: scratch of polycorr_part_len(g, da, dbb, K1) doubles.
 hipError_t launch_polycorr(const Geom& g, const double* vrow, int da, int dbb, int K0, int K1,
                            double* part, double* pi, hipStream_t st);
@@ -93,6 +93,11 @@ hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const d
                              const double* rhs, double* coef, int accumulate, const int* flag,
                              hipStream_t st);
 hipError_t launch_clear_flag(int* flag, hipStream_t st);
+// io[0..5] = the request's r_fit, s_fit, r, s, coef, d (slots kIo*).
+hipError_t launch_set_io(void** io, const void* rf, const void* sf, const void* r, const void* s,
+                         double* coef, void* d, hipStream_t st);
+// dst[0..n) = src[0..n) (nothing when dst resolves to null).
+hipError_t launch_copy_f64(IoRef<double> dst, const double* src, int n, hipStream_t st);
 
 // Subtraction.
 hipError_t launch_stamps(const Geom& g, const double* coef, double* kap, hipStream_t st);

@@ -46,6 +46,7 @@ struct Workspace {
     double* kap1;              // its 1-D stamps: [max(DK,DB) + 1 + 2 w0][P][L1]
     double *G, *h, *L, *dsc, *rhs, *coef, *dfac, *dinv;
     int* flag;
+    void** io;                 // caller buffers of the request in flight (graph replays)
 };
 
 inline int poly_degree(const Geom& g) { return g.dk > g.db ? g.dk : g.db; }
@@ -88,6 +89,7 @@ inline size_t carve(Workspace& w, const Geom& g, size_t cxb, size_t reb, char* b
     w.dfac = c.take<double>(base, (size_t)((g.nu + 63) / 64) * 64 * 64);
     w.dinv = c.take<double>(base, (size_t)((g.nu + 63) / 64) * 2 * 64 * 64);
     w.flag = c.take<int>(base, 64);
+    w.io = c.take<void*>(base, kIoSlots);
     return c.off + 256;
 }
 
@@ -148,6 +150,10 @@ struct Plan {
     Twiddles t0, t1;
     Workspace ws;
     int device = 0;
+    // The whole path captured once per variant (apply pair = fit pair, or
+    // not) with every caller buffer read from ws.io; a request then costs
+    // one table write and one graph launch.
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
 int check_params(const sfft_params* p);
@@ -155,6 +161,9 @@ int64_t num_unknowns(const sfft_params* p);
 size_t workspace_bytes(const sfft_params* p);
 int plan_run(Plan& pl, const void* rf, const void* sf, const void* r, const void* s, double* coef,
              void* d, hipStream_t st);
+// The same through the plan's captured graph (captured on first use).
+int plan_run_graph(Plan& pl, const void* rf, const void* sf, const void* r, const void* s,
+                   double* coef, void* d, hipStream_t st);
 int flag_status(int f);
 class Engine;
 

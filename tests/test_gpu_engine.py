@@ -89,3 +89,36 @@ def test_requests_queue_until_memory_frees(sfft):
         for t, c, d in outs:
             assert ctx.wait(t) == sfft.OK
             assert torch.equal(c, cref) and torch.equal(d, dref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replays_match_eager(sfft, prec):
+    """The engine replays one captured graph per workspace and variant (apply
+    pair = fit pair, or not); the caller's buffers change on every replay and
+    eager work runs between the replays. Every replay must equal the eager
+    (directly launched) result bit for bit."""
+    pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
+    shapes = [(96, 128, 3, 2, 2), (64, 64, 2, 1, 1)]
+    with sfft.Context(0) as eager, sfft.Context(0) as ctx:
+        ctx.engine_config(2)
+        for rep in range(4):
+            for k, (n0, n1, w, dk, db) in enumerate(shapes):
+                p = sfft.Params(n0, n1, w, w, dk, db, 0, pr, sfft.F32)
+                Rf, Sf = _inputs(10 * k + rep, n0, n1, w, dk, db)
+                same = rep % 2 == 0
+                if same:
+                    R, S = Rf, Sf
+                else:   # apply the fit to a second pair of the same shape
+                    R, S = _inputs(100 + 10 * k + rep, n0, n1, w, dk, db)
+                cref, dref = eager.run(p, Rf, Sf, R, S)
+                eager.sync()
+                want_coef = rep != 3
+                c = torch.full((p.num_unknowns,), float("nan"), dtype=torch.float64,
+                               device="cuda") if want_coef else None
+                d = torch.full((n0, n1), float("nan"), dtype=torch.float32, device="cuda")
+                t = ctx.submit(p, Rf, Sf, R, S, c, d)
+                assert ctx.wait(t) == sfft.OK
+                torch.cuda.synchronize()
+                if want_coef:
+                    assert torch.equal(c, cref), (prec, rep, k)
+                assert torch.equal(d, dref), (prec, rep, k)
