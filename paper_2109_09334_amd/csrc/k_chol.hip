@@ -48,46 +48,68 @@ __global__ void __launch_bounds__(256) scale_kernel(int n, const double* __restr
     if (bad) atomicOr(flag, kFlagNonFinite);
 }
 
+// FP64 matrix-core product of two 64-row panels staged in LDS:
+//   acc[I] = sum_c P[16 I + r][c] Q[16 wv + s][c]   (r, s < 16)
+// for the 16-column strip wv of the 64 x 64 result and its four row blocks
+// I (v_mfma_f64_16x16x4: lane l holds A[l%16][l/16], B[l/16][l%16], and
+// result row l/16 + 4 q, column l%16 in register q).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void panel_mfma(const double (*P)[NBK + 1], const double (*Q)[NBK + 1],
+                                           int wv, int lane, dbl4* acc) {
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int I = 0; I < 4; ++I) acc[I] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int kk = 0; kk < NBK / 4; ++kk) {
+        const int cc = 4 * kk + lk;
+        const double b = Q[16 * wv + lr][cc];
+#pragma unroll
+        for (int I = 0; I < 4; ++I)
+            acc[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(P[16 * I + lr][cc], b, acc[I], 0, 0, 0);
+    }
+}
+
+// PI = L_(i0 .. i0+ni, kp .. kp+63), PJ = L_(j0 .. j0+nj, kp .. kp+63), rows
+// past ni / nj zero: each thread issues its 32 loads before the LDS writes
+// (one memory latency instead of one per element), then a barrier.
+__device__ __forceinline__ void stage_panels(const double* __restrict__ L, int n, int kp, int i0,
+                                             int ni, int j0, int nj, double (*PI)[NBK + 1],
+                                             double (*PJ)[NBK + 1]) {
+    constexpr int kPer = NBK * NBK / 256;
+    double vi[kPer], vj[kPer];
+    const int c = threadIdx.x & 63, r = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int i = r + 4 * q;
+        vi[q] = i < ni ? L[(size_t)(i0 + i) * n + kp + c] : 0.0;
+        vj[q] = i < nj ? L[(size_t)(j0 + i) * n + kp + c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        PI[r + 4 * q][c] = vi[q];
+        PJ[r + 4 * q][c] = vj[q];
+    }
+    __syncthreads();
+}
+
 // A_(i0.., j0..) -= L_(i0.., kp..kp+63) L_(j0.., kp..kp+63)^T on one 64 x 64
 // tile of the lower triangle (diag: i0 == j0, only c <= i is stored).
 __device__ __forceinline__ void tile_update(int n, double* __restrict__ L, int kp, int i0, int j0,
                                             double (*PI)[NBK + 1], double (*PJ)[NBK + 1]) {
     const int ni = min(NBK, n - i0), nj = min(NBK, n - j0);
-    for (int t = threadIdx.x; t < NBK * NBK; t += blockDim.x) {
-        const int i = t >> 6, c = t & 63;
-        PI[i][c] = i < ni ? L[(size_t)(i0 + i) * n + kp + c] : 0.0;
-        PJ[i][c] = i < nj ? L[(size_t)(j0 + i) * n + kp + c] : 0.0;
-    }
-    __syncthreads();
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double acc[4][4];
+    stage_panels(L, n, kp, i0, ni, j0, nj, PI, PJ);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    dbl4 acc[4];
+    panel_mfma(PI, PJ, wv, lane, acc);
+    const int jc = 16 * wv + (lane & 15);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int I = 0; I < 4; ++I)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int c = 0; c < NBK; ++c) {
-        double x[4], y[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            x[a] = PI[ty + 16 * a][c];
-            y[a] = PJ[tx + 16 * a][c];
+        for (int q = 0; q < 4; ++q) {
+            const int i = 16 * I + (lane >> 4) + 4 * q;
+            if (i < ni && jc < nj && !(i0 == j0 && jc > i))
+                L[(size_t)(i0 + i) * n + j0 + jc] -= acc[I][q];
         }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int i = ty + 16 * a;
-        if (i >= ni) continue;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int jc = tx + 16 * b;
-            if (jc >= nj || (i0 == j0 && jc > i)) continue;
-            L[(size_t)(i0 + i) * n + j0 + jc] -= acc[a][b];
-        }
-    }
 }
 
 // Step k of the right-looking factorisation, with the trailing update of
@@ -143,27 +165,42 @@ __global__ void __launch_bounds__(256) chol_step_kernel(int n, double* __restric
     if (k > 0) {
         // panel k-1 (64 full columns at kp) onto D and onto this row block
         const int kp = kb - NBK;
-        for (int t = threadIdx.x; t < NBK * NBK; t += blockDim.x) {
-            const int i = t >> 6, c = t & 63;
-            PJ[i][c] = i < nb ? L[(size_t)(kb + i) * n + kp + c] : 0.0;
-            PI[i][c] = i < nr ? L[(size_t)(r0 + i) * n + kp + c] : 0.0;
-        }
-        __syncthreads();
-        for (int c = 0; c < NBK; ++c) {
-            double pr[4], pc[4], qr[4];
+        stage_panels(L, n, kp, r0, nr, kb, nb, PI, PJ);
+        // the update on the matrix cores, a 16-column strip per wave; the
+        // strips go through LDS into the factor's register tiles
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        dbl4 ud[4], ux[4];
+        panel_mfma(PJ, PJ, wv, lane, ud);
+        panel_mfma(PI, PJ, wv, lane, ux);
+        __syncthreads();   // every wave is done reading the panels
+        const int jc = 16 * wv + (lane & 15);
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                pr[a] = PJ[ty + 16 * a][c];
-                pc[a] = PJ[tx + 16 * a][c];
-                qr[a] = PI[ty + 16 * a][c];
+        for (int I = 0; I < 4; ++I)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * I + (lane >> 4) + 4 * q;
+                PJ[i][jc] = ud[I][q];
+                PI[i][jc] = ux[I][q];
             }
+        __syncthreads();
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    d[a][b] -= pr[a] * pc[b];
-                    x[a][b] -= qr[a] * pc[b];
-                }
+            for (int b = 0; b < 4; ++b) {
+                d[a][b] -= PJ[ty + 16 * a][tx + 16 * b];
+                x[a][b] -= PI[ty + 16 * a][tx + 16 * b];
+            }
+    }
+    // Column j is published in buffer j & 1 by its owner (tx == j % 16) as
+    // soon as its last update is done: right after the update of its own
+    // 16-column group, before the FMAs of the groups to the right, so the
+    // LDS write overlaps them. Double buffering keeps the readers of column
+    // j - 1 (all past the barrier of column j) clear of the write of j + 1.
+    if (tx == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            colD[0][ty + 16 * a] = d[a][0];
+            colA[0][ty + 16 * a] = x[a][0];
         }
     }
 #pragma unroll
@@ -174,23 +211,16 @@ __global__ void __launch_bounds__(256) chol_step_kernel(int n, double* __restric
             if (j >= nb) break;   // uniform over the workgroup
             const int buf = j & 1;
             const bool owner = tx == jj;
-            if (owner) {
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    colD[buf][ty + 16 * a] = d[a][bj];
-                    colA[buf][ty + 16 * a] = x[a][bj];
-                }
-            }
             __syncthreads();
             // all LDS reads first (unconditional, so they issue together)
             double cd[4], cx[4], cc[4];
+            double piv = colD[buf][j];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 cd[a] = colD[buf][ty + 16 * a];
                 cx[a] = colA[buf][ty + 16 * a];
                 cc[a] = colD[buf][tx + 16 * a];
             }
-            double piv = colD[buf][j];
             if (!(piv > 0.0) || !isfinite(piv)) {
                 if (threadIdx.x == 0) atomicOr(flag, isfinite(piv) ? kFlagNotSpd : kFlagNonFinite);
                 piv = 1.0;
@@ -212,12 +242,32 @@ __global__ void __launch_bounds__(256) chol_step_kernel(int n, double* __restric
                 }
             }
 #pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                d[a][bj] -= li[a] * lc[bj];
+                x[a][bj] -= xi[a] * lc[bj];
+            }
+            if (jj < 15 && tx == jj + 1) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    colD[buf ^ 1][ty + 16 * a] = d[a][bj];
+                    colA[buf ^ 1][ty + 16 * a] = x[a][bj];
+                }
+            }
+#pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = bj; b < 4; ++b) {
+                for (int b = bj + 1; b < 4; ++b) {
                     d[a][b] -= li[a] * lc[b];
                     x[a][b] -= xi[a] * lc[b];
                 }
+            if (bj < 3 && jj == 15 && tx == 0) {   // next column opens group bj + 1
+                const int bn = bj < 3 ? bj + 1 : 3;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    colD[buf ^ 1][ty + 16 * a] = d[a][bn];
+                    colA[buf ^ 1][ty + 16 * a] = x[a][bn];
+                }
+            }
         }
     }
     if (blockIdx.x == 0) {
