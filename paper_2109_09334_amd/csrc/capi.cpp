@@ -402,7 +402,7 @@ static hipError_t factor_solve(Plan& pl, const double* G, const double* h, doubl
     }
     if (!e) {
         StageTimer t_(pl.prof, "trsv", st);
-        e = launch_chol_solve(n, w.L, w.dinv, w.dsc, h, coef, 0, w.flag, st);
+        e = launch_chol_solve(n, w.L, w.dinv, w.dsc, h, coef, 0, w.flag, w.tsv, w.tflag, st);
     }
     return e;
 }
@@ -445,7 +445,8 @@ static hipError_t refine(Plan& pl, double* coef, hipStream_t st) {
     if (!e) e = launch_lagfix(g, 1, w.ped, w.piR, w.piD, w.sig0, w.sig1, w.pw, dm, nullptr,
                               w.thetaD, nullptr, nullptr, w.evecD, st);
     if (!e) e = launch_gather(g, w.omega, w.thetaD, w.lam, w.cmat, w.evecD, nullptr, w.rhs, 1, st);
-    if (!e) e = launch_chol_solve(g.nu, w.L, w.dinv, w.dsc, w.rhs, coef, 1, w.flag, st);
+    if (!e) e = launch_chol_solve(g.nu, w.L, w.dinv, w.dsc, w.rhs, coef, 1, w.flag, w.tsv, w.tflag,
+                                  st);
     return e;
 }
 
@@ -582,6 +583,7 @@ int plan_read_flag(Plan& pl, hipStream_t st, int* flag) {
 }
 
 int flag_status(int f) {
+    if (f & 4) return SFFT_E_HIP;   // a solve block waited past its bound
     if (f & 2) return SFFT_E_NONFINITE;
     if (f & 1) return SFFT_E_NOT_SPD;
     return SFFT_OK;

@@ -382,80 +382,110 @@ __global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__
     }
 }
 
-// Row block of the left-looking triangular sweep: for the nb rows r0 + i,
-//   u_i = y[r0 + i] - sum_(c in [c_lo, c_hi)) M[(r0 + i) n + c] y[c],
-// then y[r0 + i] = sum_k W[i][k] u_k (W: 64 x 64 row-major). y lives in LDS.
-// 16 threads per row (1024 threads: 64 rows); each thread issues 16 loads of
-// its stride-16 slice of the row before using them, so a row block costs a
-// few memory round trips; then one 64 x 64 mat-vec. The y[c] read are final
-// (other blocks), the writes touch only this block.
-__device__ __forceinline__ void trsv_block(const double* __restrict__ M, int n, int r0, int nb,
-                                           int c_lo, int c_hi, const double* __restrict__ W,
-                                           double* ys, double* ub) {
-    const int i = threadIdx.x >> 4, pt = threadIdx.x & 15;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i < nb) {
-        const double* Mi = M + (size_t)(r0 + i) * n;
-        int c = c_lo + pt;
-        for (; c + 240 < c_hi; c += 256) {
-            double v[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = Mi[c + 16 * q];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc[q & 3] += v[q] * ys[c + 16 * q];
-        }
-        for (; c < c_hi; c += 16) acc[0] += Mi[c] * ys[c];
-    }
-    double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 4, 64);
-    s += __shfl_xor(s, 8, 64);
-    if (pt == 0) ub[i] = i < nb ? ys[r0 + i] - s : 0.0;
-    __syncthreads();
-    double t = 0.0;
-    const double* Wi = W + i * NBK + pt * 4;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) t += Wi[q] * ub[pt * 4 + q];
-    t += __shfl_xor(t, 1, 64);
-    t += __shfl_xor(t, 2, 64);
-    t += __shfl_xor(t, 4, 64);
-    t += __shfl_xor(t, 8, 64);
-    if (pt == 0 && i < nb) ys[r0 + i] = t;
-    __syncthreads();
+// Triangular solves as a dataflow over 64-row blocks, one workgroup per
+// block and direction (T = ceil(n/64) blocks):
+//   forward  y_B = W_B (D b_B - sum_(C < B) L_BC y_C),        workgroup B
+//   backward z_B = W_B^T (y_B - sum_(C > B) (L^T)_BC z_C),     workgroup 2T-1-B
+// then coef_B (+)= D z_B, with W_B, W_B^T the inverted diagonal blocks and
+// (L^T)_BC read from the mirrored upper triangle (rows, coalesced). Each
+// workgroup takes its dependency blocks in a fixed order (forward C = 0, 1,
+// ..., backward y_B first, then C = T-1, T-2, ...), so the sums do not depend
+// on timing; while it waits for block C it already holds that tile's row
+// slices and its W in registers. A block's result goes to tsv, then its
+// completion flag is set (release); readers poll the flag, then acquire.
+// Every wait is on a workgroup of lower index (dispatched earlier), and each
+// poll is bounded: past the bound the block sets kFlagStall and goes on.
+constexpr int kFlagStall = 4;
+constexpr int kSolveSpin = 1 << 22;
+
+__global__ void tflag_clear_kernel(int* tflag, int m) {
+    for (int i = threadIdx.x; i < m; i += blockDim.x) tflag[i] = 0;
 }
 
-// Solve (D G D) z = D b with the factor L (lower part; the upper part holds
-// L^T), then coef (+)= D z. One workgroup of 1024 threads, left-looking over
-// 64-row blocks: forward y_B = W_B (D b_B - L_(B, <B) y_<B), backward
-// z_B = W_B^T (y_B - (L^T)_(B, >B) z_>B), both reading rows of the stored
-// triangle. W_B, W_B^T: inverses of the diagonal blocks (dinv). The work
-// vector (n doubles) is held in dynamic LDS.
-__global__ void __launch_bounds__(1024) trsv_kernel(int n, const double* __restrict__ L,
-                                                     const double* __restrict__ dinv,
-                                                     const double* __restrict__ dsc,
-                                                     const double* __restrict__ b,
-                                                     double* __restrict__ coef, int accumulate,
-                                                     const int* __restrict__ flag) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* ub = reinterpret_cast<double*>(smem_raw);
-    double* ys = ub + NBK;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) ys[i] = dsc[i] * b[i];
+// Waits (thread 0, bounded) until *f is set, then makes the producer's
+// writes visible to the whole workgroup.
+__device__ __forceinline__ void wait_flag(const int* f, int* flag) {
+    if (threadIdx.x == 0) {
+        int spins = 0;
+        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins == kSolveSpin) {
+                atomicOr(flag, kFlagStall);
+                break;
+            }
+        }
+    }
     __syncthreads();
-    const int nblk = (n + NBK - 1) / NBK;
-    for (int B = 0; B < nblk; ++B) {
-        const int r0 = B * NBK, nb = min(NBK, n - r0);
-        trsv_block(L, n, r0, nb, 0, r0, dinv + (size_t)B * 2 * NBK * NBK, ys, ub);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __restrict__ L,
+                                                         const double* __restrict__ dinv,
+                                                         const double* __restrict__ dsc,
+                                                         const double* __restrict__ b,
+                                                         double* __restrict__ coef, int accumulate,
+                                                         int* flag, double* tsv, int* tflag) {
+    __shared__ double vsh[NBK];
+    const int T = (n + NBK - 1) / NBK;
+    const bool fwd = (int)blockIdx.x < T;
+    const int B = fwd ? blockIdx.x : 2 * T - 1 - blockIdx.x;
+    const int r0 = B * NBK, nb = min(NBK, n - r0);
+    const int i = threadIdx.x >> 2, p = threadIdx.x & 3;   // row, quarter of the columns
+    double* ys = tsv;
+    double* zs = tsv + n;
+    int* fdone = tflag;       // forward block C done
+    int* bdone = tflag + T;   // backward block C done
+    // this block's inverse (row i, columns 16 p ..), loaded while waiting
+    const double* W = dinv + (size_t)B * 2 * NBK * NBK + (fwd ? 0 : NBK * NBK);
+    double w[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) w[q] = W[i * NBK + 16 * p + q];
+    double acc = 0.0;
+    const int nd = fwd ? B : T - 1 - B;
+    for (int t = 0; t < nd; ++t) {
+        const int C = fwd ? t : T - 1 - t;
+        const int c0 = C * NBK + 16 * p;
+        double m[16];
+        const double* row = L + (size_t)(r0 + min(i, nb - 1)) * n;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) m[q] = (i < nb && c0 + q < n) ? row[c0 + q] : 0.0;
+        wait_flag(fwd ? fdone + C : bdone + C, flag);
+        if (threadIdx.x < NBK) {
+            const int cc = C * NBK + threadIdx.x;
+            vsh[threadIdx.x] = cc < n ? (fwd ? ys : zs)[cc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc += m[q] * vsh[16 * p + q];
+        __syncthreads();   // vsh is rewritten next
     }
-    for (int B = nblk - 1; B >= 0; --B) {
-        const int r0 = B * NBK, nb = min(NBK, n - r0);
-        trsv_block(L, n, r0, nb, r0 + nb, n, dinv + (size_t)B * 2 * NBK * NBK + NBK * NBK, ys, ub);
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (!fwd) wait_flag(fdone + B, flag);   // y_B
+    if (p == 0) {
+        const double rhs = i < nb ? (fwd ? dsc[r0 + i] * b[r0 + i] : ys[r0 + i]) : 0.0;
+        vsh[i] = i < nb ? rhs - acc : 0.0;
     }
-    const bool bad = *flag != 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double z = bad ? __builtin_nan("") : dsc[i] * ys[i];
-        coef[i] = accumulate ? coef[i] + z : z;
+    __syncthreads();
+    double y = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) y += w[q] * vsh[16 * p + q];
+    y += __shfl_xor(y, 1, 64);
+    y += __shfl_xor(y, 2, 64);
+    if (p == 0 && i < nb) {
+        if (fwd) {
+            ys[r0 + i] = y;
+        } else {
+            zs[r0 + i] = y;
+            const bool bad = *flag != 0;
+            const double z = bad ? __builtin_nan("") : dsc[r0 + i] * y;
+            coef[r0 + i] = accumulate ? coef[r0 + i] + z : z;
+        }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(fwd ? fdone + B : bdone + B, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 hipError_t launch_clear_flag(int* flag, hipStream_t st) {
@@ -486,17 +516,12 @@ hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* fl
 }
 
 hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const double* dsc,
-                             const double* rhs, double* coef, int accumulate, const int* flag,
-                             hipStream_t st) {
-    const size_t lds = (size_t)(n + NBK) * sizeof(double);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(trsv_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(trsv_kernel, dim3(1), dim3(1024), lds, st, n, L, dinv, dsc, rhs, coef,
-                       accumulate, flag);
+                             const double* rhs, double* coef, int accumulate, int* flag,
+                             double* tsv, int* tflag, hipStream_t st) {
+    const int T = (n + NBK - 1) / NBK;
+    hipLaunchKernelGGL(tflag_clear_kernel, dim3(1), dim3(64), 0, st, tflag, 2 * T);
+    hipLaunchKernelGGL(trsv_flow_kernel, dim3(2 * T), dim3(256), 0, st, n, L, dinv, dsc, rhs, coef,
+                       accumulate, flag, tsv, tflag);
     return hipGetLastError();
 }
 

@@ -88,10 +88,12 @@ hipError_t launch_jacobi(int n, const double* G, const double* h, double* L, dou
 // with the factor in its lower and its transpose in its upper triangle.
 hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* flag,
                            hipStream_t st);
-// coef (+)= solution of G c = rhs (rhs is read only).
+// coef (+)= solution of G c = rhs (rhs is read only). tsv: scratch of 2 n
+// doubles, tflag: of 2 ceil(n/64) ints. flag gains kFlagStall if a block
+// of the solve waited past its bound (a broken dependency, never expected).
 hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const double* dsc,
-                             const double* rhs, double* coef, int accumulate, const int* flag,
-                             hipStream_t st);
+                             const double* rhs, double* coef, int accumulate, int* flag,
+                             double* tsv, int* tflag, hipStream_t st);
 hipError_t launch_clear_flag(int* flag, hipStream_t st);
 // io[0..5] = the request's r_fit, s_fit, r, s, coef, d (slots kIo*).
 hipError_t launch_set_io(void** io, const void* rf, const void* sf, const void* r, const void* s,

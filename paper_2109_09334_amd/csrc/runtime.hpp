@@ -47,6 +47,8 @@ struct Workspace {
     double *G, *h, *L, *dsc, *rhs, *coef, *dfac, *dinv;
     int* flag;
     void** io;                 // caller buffers of the request in flight (graph replays)
+    double* tsv;               // triangular solves: forward and backward block results
+    int* tflag;                // their per-block completion flags
 };
 
 inline int poly_degree(const Geom& g) { return g.dk > g.db ? g.dk : g.db; }
@@ -90,6 +92,8 @@ inline size_t carve(Workspace& w, const Geom& g, size_t cxb, size_t reb, char* b
     w.dinv = c.take<double>(base, (size_t)((g.nu + 63) / 64) * 2 * 64 * 64);
     w.flag = c.take<int>(base, 64);
     w.io = c.take<void*>(base, kIoSlots);
+    w.tsv = c.take<double>(base, 2 * (size_t)g.nu);
+    w.tflag = c.take<int>(base, 2 * ((g.nu + 63) / 64));
     return c.off + 256;
 }
 
