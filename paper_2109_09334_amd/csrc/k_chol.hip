@@ -15,6 +15,8 @@ namespace sfft {
 constexpr int NBK = 64;
 constexpr int kFlagNotSpd = 1;
 constexpr int kFlagNonFinite = 2;
+constexpr int kFlagStall = 4;          // a bounded wait ran out (never expected)
+constexpr int kSolveSpin = 1 << 22;    // bound of every poll loop
 
 __global__ void clear_flag_kernel(int* flag) { *flag = 0; }
 
@@ -54,40 +56,46 @@ __global__ void __launch_bounds__(256) scale_kernel(int n, const double* __restr
 // I (v_mfma_f64_16x16x4: lane l holds A[l%16][l/16], B[l/16][l%16], and
 // result row l/16 + 4 q, column l%16 in register q).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kStepThreads = 512;   // eight waves per panel / tile workgroup
+
+// Row blocks I0 .. I0+NI-1 of the strip s:
+//   acc[I] = sum_c P[16 (I0 + I) + r][c] Q[16 s + t][c]   (r, t < 16).
+template <int NI>
 __device__ __forceinline__ void panel_mfma(const double (*P)[NBK + 1], const double (*Q)[NBK + 1],
-                                           int wv, int lane, dbl4* acc) {
+                                           int I0, int s, int lane, dbl4* acc) {
     const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-    for (int I = 0; I < 4; ++I) acc[I] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int I = 0; I < NI; ++I) acc[I] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
     for (int kk = 0; kk < NBK / 4; ++kk) {
         const int cc = 4 * kk + lk;
-        const double b = Q[16 * wv + lr][cc];
+        const double b = Q[16 * s + lr][cc];
 #pragma unroll
-        for (int I = 0; I < 4; ++I)
-            acc[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(P[16 * I + lr][cc], b, acc[I], 0, 0, 0);
+        for (int I = 0; I < NI; ++I)
+            acc[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(P[16 * (I0 + I) + lr][cc], b, acc[I], 0, 0,
+                                                          0);
     }
 }
 
 // PI = L_(i0 .. i0+ni, kp .. kp+63), PJ = L_(j0 .. j0+nj, kp .. kp+63), rows
-// past ni / nj zero: each thread issues its 32 loads before the LDS writes
+// past ni / nj zero: each thread issues all its loads before the LDS writes
 // (one memory latency instead of one per element), then a barrier.
 __device__ __forceinline__ void stage_panels(const double* __restrict__ L, int n, int kp, int i0,
                                              int ni, int j0, int nj, double (*PI)[NBK + 1],
                                              double (*PJ)[NBK + 1]) {
-    constexpr int kPer = NBK * NBK / 256;
+    constexpr int kRows = kStepThreads / 64, kPer = NBK / kRows;
     double vi[kPer], vj[kPer];
     const int c = threadIdx.x & 63, r = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        const int i = r + 4 * q;
+        const int i = r + kRows * q;
         vi[q] = i < ni ? L[(size_t)(i0 + i) * n + kp + c] : 0.0;
         vj[q] = i < nj ? L[(size_t)(j0 + i) * n + kp + c] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        PI[r + 4 * q][c] = vi[q];
-        PJ[r + 4 * q][c] = vj[q];
+        PI[r + kRows * q][c] = vi[q];
+        PJ[r + kRows * q][c] = vj[q];
     }
     __syncthreads();
 }
@@ -98,15 +106,17 @@ __device__ __forceinline__ void tile_update(int n, double* __restrict__ L, int k
                                             double (*PI)[NBK + 1], double (*PJ)[NBK + 1]) {
     const int ni = min(NBK, n - i0), nj = min(NBK, n - j0);
     stage_panels(L, n, kp, i0, ni, j0, nj, PI, PJ);
+    // eight waves: column strip wv % 4, row blocks 2 (wv / 4) and 2 (wv / 4) + 1
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    dbl4 acc[4];
-    panel_mfma(PI, PJ, wv, lane, acc);
-    const int jc = 16 * wv + (lane & 15);
+    const int I0 = 2 * (wv >> 2), sc = wv & 3;
+    dbl4 acc[2];
+    panel_mfma<2>(PI, PJ, I0, sc, lane, acc);
+    const int jc = 16 * sc + (lane & 15);
 #pragma unroll
-    for (int I = 0; I < 4; ++I)
+    for (int I = 0; I < 2; ++I)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int i = 16 * I + (lane >> 4) + 4 * q;
+            const int i = 16 * (I0 + I) + (lane >> 4) + 4 * q;
             if (i < ni && jc < nj && !(i0 == j0 && jc > i))
                 L[(size_t)(i0 + i) * n + j0 + jc] -= acc[I][q];
         }
@@ -116,23 +126,29 @@ __device__ __forceinline__ void tile_update(int n, double* __restrict__ L, int k
 // step k - 1 folded in: one launch per 64-column panel (kb = 64 k).
 //  * Workgroups b < T - k (T = number of 64-blocks) work on panel k, row
 //    block k + b. For k > 0 they first apply panel k-1's update to their own
-//    tile of column block k and to the diagonal tile (in registers: every
-//    panel workgroup forms the updated diagonal tile itself, nothing is
-//    written there during the launch). Then every one factorises the
-//    diagonal block D; workgroup 0 stores it in dfac (copied into L after
-//    the last step), workgroup b >= 1 also solves its row block X L_D^T = A.
-//    Factor and solve are one right-looking pass over the 64 columns: 256
-//    threads own 4x4 register tiles (rows ty + 16 a, columns tx + 16 b) of D
+//    tile of column block k and to the diagonal tile (every panel workgroup
+//    forms the updated diagonal tile itself, nothing is written there during
+//    the launch): the panel rows are staged in LDS and multiplied on the
+//    FP64 matrix cores. Then every one factorises the diagonal block D;
+//    workgroup 0 stores it in dfac (copied into L after the last step),
+//    workgroup b >= 1 also solves its row block X L_D^T = A.
+//    Factor and solve are one right-looking pass over the 64 columns: 512
+//    threads own 2x4 register tiles (rows ty + 32 a, columns tx + 16 b) of D
 //    and A; the raw column j is published through LDS (double buffered, one
 //    barrier per column) and every thread scales it by the pivot itself. The
 //    column group bj = j / 16 is unrolled, so tiles are addressed statically
-//    and the updates skip the groups left of the pivot.
+//    and the updates skip the groups left of the pivot. The pass is a chain
+//    of 64 dependent column steps (LDS round trip, barrier, pivot inverse
+//    square root, FMAs): about 1000 cycles each, the floor of this design.
 //  * The other workgroups give the tiles (I, J), I >= J > k, of the trailing
 //    matrix panel k-1's update.
 // After the launch column block k is final and every tile right of it has
 // the updates of panels 0 .. k-1.
-__global__ void __launch_bounds__(256) chol_step_kernel(int n, double* __restrict__ L, int k,
-                                                         double* __restrict__ dfac, int* flag) {
+__global__ void __launch_bounds__(kStepThreads) chol_step_kernel(int n, double* __restrict__ L,
+                                                                  int k, double* __restrict__ dfac,
+                                                                  int* flag) {
+    constexpr int RY = kStepThreads / 16;   // row groups: thread rows ty + RY a
+    constexpr int RA = NBK / RY;            // rows per thread
     __shared__ double PI[NBK][NBK + 1];
     __shared__ double PJ[NBK][NBK + 1];
     __shared__ double colD[2][NBK];
@@ -153,12 +169,12 @@ __global__ void __launch_bounds__(256) chol_step_kernel(int n, double* __restric
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int r0 = kb + blockIdx.x * NBK;
     const int nr = blockIdx.x == 0 ? 0 : min(NBK, n - r0);
-    double d[4][4], x[4][4];
+    double d[RA][4], x[RA][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < RA; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int i = ty + 16 * a, c = tx + 16 * b;
+            const int i = ty + RY * a, c = tx + 16 * b;
             d[a][b] = (i < nb && c <= i) ? L[(size_t)(kb + i) * n + kb + c] : 0.0;
             x[a][b] = (i < nr && c < nb) ? L[(size_t)(r0 + i) * n + kb + c] : 0.0;
         }
@@ -166,41 +182,43 @@ __global__ void __launch_bounds__(256) chol_step_kernel(int n, double* __restric
         // panel k-1 (64 full columns at kp) onto D and onto this row block
         const int kp = kb - NBK;
         stage_panels(L, n, kp, r0, nr, kb, nb, PI, PJ);
-        // the update on the matrix cores, a 16-column strip per wave; the
-        // strips go through LDS into the factor's register tiles
+        // the update on the matrix cores (wave: column strip wv % 4, row
+        // blocks 2 (wv / 4) + {0, 1}); the strips go through LDS into the
+        // factor's register tiles
         const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        dbl4 ud[4], ux[4];
-        panel_mfma(PJ, PJ, wv, lane, ud);
-        panel_mfma(PI, PJ, wv, lane, ux);
+        const int I0 = 2 * (wv >> 2), sc = wv & 3;
+        dbl4 ud[2], ux[2];
+        panel_mfma<2>(PJ, PJ, I0, sc, lane, ud);
+        panel_mfma<2>(PI, PJ, I0, sc, lane, ux);
         __syncthreads();   // every wave is done reading the panels
-        const int jc = 16 * wv + (lane & 15);
+        const int jc = 16 * sc + (lane & 15);
 #pragma unroll
-        for (int I = 0; I < 4; ++I)
+        for (int I = 0; I < 2; ++I)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int i = 16 * I + (lane >> 4) + 4 * q;
+                const int i = 16 * (I0 + I) + (lane >> 4) + 4 * q;
                 PJ[i][jc] = ud[I][q];
                 PI[i][jc] = ux[I][q];
             }
         __syncthreads();
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < RA; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                d[a][b] -= PJ[ty + 16 * a][tx + 16 * b];
-                x[a][b] -= PI[ty + 16 * a][tx + 16 * b];
+                d[a][b] -= PJ[ty + RY * a][tx + 16 * b];
+                x[a][b] -= PI[ty + RY * a][tx + 16 * b];
             }
     }
-    // Column j is published in buffer j & 1 by its owner (tx == j % 16) as
+    // Column j is published in buffer j & 1 by its owners (tx == j % 16) as
     // soon as its last update is done: right after the update of its own
     // 16-column group, before the FMAs of the groups to the right, so the
     // LDS write overlaps them. Double buffering keeps the readers of column
     // j - 1 (all past the barrier of column j) clear of the write of j + 1.
     if (tx == 0) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            colD[0][ty + 16 * a] = d[a][0];
-            colA[0][ty + 16 * a] = x[a][0];
+        for (int a = 0; a < RA; ++a) {
+            colD[0][ty + RY * a] = d[a][0];
+            colA[0][ty + RY * a] = x[a][0];
         }
     }
 #pragma unroll
@@ -213,48 +231,50 @@ __global__ void __launch_bounds__(256) chol_step_kernel(int n, double* __restric
             const bool owner = tx == jj;
             __syncthreads();
             // all LDS reads first (unconditional, so they issue together)
-            double cd[4], cx[4], cc[4];
+            double cd[RA], cx[RA], cc[4];
             double piv = colD[buf][j];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                cd[a] = colD[buf][ty + 16 * a];
-                cx[a] = colA[buf][ty + 16 * a];
-                cc[a] = colD[buf][tx + 16 * a];
+            for (int a = 0; a < RA; ++a) {
+                cd[a] = colD[buf][ty + RY * a];
+                cx[a] = colA[buf][ty + RY * a];
             }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) cc[b] = colD[buf][tx + 16 * b];
             if (!(piv > 0.0) || !isfinite(piv)) {
                 if (threadIdx.x == 0) atomicOr(flag, isfinite(piv) ? kFlagNotSpd : kFlagNonFinite);
                 piv = 1.0;
             }
             const double inv = rsqrt(piv), ljj = piv * inv;
-            double li[4], xi[4], lc[4];
+            double li[RA], xi[RA], lc[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                li[a] = ty + 16 * a > j ? cd[a] * inv : 0.0;
+            for (int a = 0; a < RA; ++a) {
+                li[a] = ty + RY * a > j ? cd[a] * inv : 0.0;
                 xi[a] = cx[a] * inv;
-                lc[a] = tx + 16 * a > j ? cc[a] * inv : 0.0;
             }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) lc[b] = tx + 16 * b > j ? cc[b] * inv : 0.0;
             if (owner) {
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const int i = ty + 16 * a;
+                for (int a = 0; a < RA; ++a) {
+                    const int i = ty + RY * a;
                     d[a][bj] = i == j ? ljj : (i > j ? li[a] : 0.0);
                     x[a][bj] = xi[a];
                 }
             }
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
+            for (int a = 0; a < RA; ++a) {
                 d[a][bj] -= li[a] * lc[bj];
                 x[a][bj] -= xi[a] * lc[bj];
             }
             if (jj < 15 && tx == jj + 1) {
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    colD[buf ^ 1][ty + 16 * a] = d[a][bj];
-                    colA[buf ^ 1][ty + 16 * a] = x[a][bj];
+                for (int a = 0; a < RA; ++a) {
+                    colD[buf ^ 1][ty + RY * a] = d[a][bj];
+                    colA[buf ^ 1][ty + RY * a] = x[a][bj];
                 }
             }
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < RA; ++a)
 #pragma unroll
                 for (int b = bj + 1; b < 4; ++b) {
                     d[a][b] -= li[a] * lc[b];
@@ -263,9 +283,9 @@ __global__ void __launch_bounds__(256) chol_step_kernel(int n, double* __restric
             if (bj < 3 && jj == 15 && tx == 0) {   // next column opens group bj + 1
                 const int bn = bj < 3 ? bj + 1 : 3;
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    colD[buf ^ 1][ty + 16 * a] = d[a][bn];
-                    colA[buf ^ 1][ty + 16 * a] = x[a][bn];
+                for (int a = 0; a < RA; ++a) {
+                    colD[buf ^ 1][ty + RY * a] = d[a][bn];
+                    colA[buf ^ 1][ty + RY * a] = x[a][bn];
                 }
             }
         }
@@ -273,19 +293,19 @@ __global__ void __launch_bounds__(256) chol_step_kernel(int n, double* __restric
     if (blockIdx.x == 0) {
         double* out = dfac + (size_t)k * NBK * NBK;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < RA; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int i = ty + 16 * a, c = tx + 16 * b;
+                const int i = ty + RY * a, c = tx + 16 * b;
                 if (i < nb && c < nb) out[i * NBK + c] = c <= i ? d[a][b] : 0.0;
             }
         return;
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < RA; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int i = ty + 16 * a, c = tx + 16 * b;
+            const int i = ty + RY * a, c = tx + 16 * b;
             if (i < nr && c < nb) L[(size_t)(r0 + i) * n + kb + c] = x[a][b];
         }
 }
@@ -395,9 +415,6 @@ __global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__
 // completion flag is set (release); readers poll the flag, then acquire.
 // Every wait is on a workgroup of lower index (dispatched earlier), and each
 // poll is bounded: past the bound the block sets kFlagStall and goes on.
-constexpr int kFlagStall = 4;
-constexpr int kSolveSpin = 1 << 22;
-
 __global__ void tflag_clear_kernel(int* tflag, int m) {
     for (int i = threadIdx.x; i < m; i += blockDim.x) tflag[i] = 0;
 }
@@ -507,7 +524,7 @@ hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* fl
     for (int k = 0; k < T; ++k) {
         const int npan = T - k;
         const int ntrail = k > 0 ? (T - k - 1) * (T - k) / 2 : 0;
-        hipLaunchKernelGGL(chol_step_kernel, dim3(npan + ntrail), dim3(256), 0, st, n, L, k, dfac,
+        hipLaunchKernelGGL(chol_step_kernel, dim3(npan + ntrail), dim3(kStepThreads), 0, st, n, L, k, dfac,
                            flag);
     }
     hipLaunchKernelGGL(diag_finish_kernel, dim3(T), dim3(256), 0, st, n, L, dfac, dinv);
