@@ -229,8 +229,12 @@ int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out)
     if (hipMalloc(&base, bytes) != hipSuccess) return SFFT_E_NOMEM;
     carve(pl->ws, pl->g, mixed ? 8 : 16, mixed ? 4 : 8, base);
     // The status flag starts clear: the allocation may hold a freed
-    // workspace's bytes, and the flag is read for every plan at a sync.
-    if (hipMemset(pl->ws.flag, 0, sizeof(int)) != hipSuccess) {
+    // workspace's bytes, and the flag is read for every plan at a sync. The
+    // 1-D polynomial sums depend on the geometry only: formed once here.
+    if (hipMemset(pl->ws.flag, 0, sizeof(int)) != hipSuccess ||
+        launch_polysum(pl->g, poly_degree(pl->g), pl->ws.sig0, pl->ws.sig1, pl->ws.pw, nullptr) !=
+            hipSuccess ||
+        hipStreamSynchronize(nullptr) != hipSuccess) {
         (void)hipFree(base);
         return SFFT_E_HIP;
     }
@@ -300,7 +304,6 @@ static hipError_t poly_tables(Plan& pl, IoRef<const Tin> r, IoRef<const Tin> s, 
     if (!e) e = launch_polycorr(g, w.vrow, g.dk, dm, 2 * g.w0, 2 * g.w1, w.vpart, w.piR, st);
     if (!e) e = launch_polyrow<Tin>(g, s, 0, dm, g.w1, w.vrow, st);
     if (!e) e = launch_polycorr(g, w.vrow, 0, dm, g.w0, g.w1, w.vpart, w.piS, st);
-    if (!e) e = launch_polysum(g, dm, w.sig0, w.sig1, w.pw, st);
     if (!e) e = launch_pedestal(g, w.piR, dm, w.piS, w.ped, st);
     return e;
 }
@@ -402,7 +405,7 @@ static hipError_t factor_solve(Plan& pl, const double* G, const double* h, doubl
     }
     if (!e) {
         StageTimer t_(pl.prof, "trsv", st);
-        e = launch_chol_solve(n, w.L, w.dinv, w.dsc, h, coef, 0, w.flag, w.tsv, w.tflag, st);
+        e = launch_chol_solve(n, w.L, w.dinv, w.dsc, h, coef, 0, w.flag, w.tsv, w.tflag, 1, st);
     }
     return e;
 }
@@ -411,7 +414,7 @@ static hipError_t factor_solve(Plan& pl, const double* G, const double* h, doubl
 // difference image of the fit pair (Z, X, ped hold the fit pair's
 // transforms), correction solved with the existing factor.
 template <typename T>
-static hipError_t refine(Plan& pl, double* coef, hipStream_t st) {
+static hipError_t refine(Plan& pl, double* coef, int gen, hipStream_t st) {
     const Geom& g = pl.g;
     Workspace& w = pl.ws;
     T* dfit = reinterpret_cast<T*>(w.dfit);
@@ -446,7 +449,7 @@ static hipError_t refine(Plan& pl, double* coef, hipStream_t st) {
                               w.thetaD, nullptr, nullptr, w.evecD, st);
     if (!e) e = launch_gather(g, w.omega, w.thetaD, w.lam, w.cmat, w.evecD, nullptr, w.rhs, 1, st);
     if (!e) e = launch_chol_solve(g.nu, w.L, w.dinv, w.dsc, w.rhs, coef, 1, w.flag, w.tsv, w.tflag,
-                                  st);
+                                  gen, st);
     return e;
 }
 
@@ -468,12 +471,12 @@ static int run_build_t(Plan& pl, const void* r, const void* s, double* G, double
 template <typename T, typename Tin>
 static int run_solve_t(Plan& pl, const double* G, const double* h, const void* r, const void* s,
                        double* coef, hipStream_t st) {
-    hipError_t e = launch_clear_flag(pl.ws.flag, st);
+    hipError_t e = launch_clear_flag(pl.ws.flag, pl.ws.tflag, tflag_len(pl.g), st);
     if (!e) e = factor_solve(pl, G, h, coef, st);
     if (!e && pl.p.precision == SFFT_MIXED && r && s) {
         e = poly_tables<Tin>(pl, (const Tin*)r, (const Tin*)s, st);
         if (!e) e = forward_fit<T, Tin>(pl, (const Tin*)r, (const Tin*)s, st);
-        for (int it = 0; !e && it < refine_steps(); ++it) e = refine<T>(pl, coef, st);
+        for (int it = 0; !e && it < refine_steps(); ++it) e = refine<T>(pl, coef, 2 + it, st);
     }
     return hip_status(e);
 }
@@ -505,11 +508,11 @@ static hipError_t all_path(Plan& pl, IoRef<const Tin> rf, IoRef<const Tin> sf, I
                            IoRef<const Tin> s, IoRef<double> coef, IoRef<Tin> d, bool same_pair,
                            hipStream_t st) {
     Workspace& w = pl.ws;
-    hipError_t e = launch_clear_flag(w.flag, st);
+    hipError_t e = launch_clear_flag(w.flag, w.tflag, tflag_len(pl.g), st);
     if (!e) e = build<T, Tin>(pl, rf, sf, w.G, w.h, st);
     if (!e) e = factor_solve(pl, w.G, w.h, w.coef, st);
     for (int it = 0; !e && pl.p.precision == SFFT_MIXED && it < refine_steps(); ++it)
-        e = refine<T>(pl, w.coef, st);
+        e = refine<T>(pl, w.coef, 2 + it, st);
     if (!e) e = launch_copy_f64(coef, w.coef, pl.g.nu, st);
     if (e) return e;
     if (same_pair) return difference<T, Tin>(pl, pl.g.dk + 1, true, w.coef, d, st);

@@ -55,7 +55,9 @@ template <typename Tin, int NE>
 __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, IoRef<const Tin> imgr, int da,
                                                       int dbb, int K1, double* __restrict__ vrow) {
     const Tin* __restrict__ img = imgr.get();
+    constexpr int kEdge = 64;   // edge pixels kept in LDS per side (K1 <= kEdge)
     __shared__ double mom[4][kMaxMom];
+    __shared__ double edge[4][2 * kEdge];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int x0 = blockIdx.x * 4 + wv;
     if (x0 >= g.n0) return;   // wave-level work only below
@@ -66,13 +68,32 @@ __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, IoRef<const Tin> i
     double mo[NE];
 #pragma unroll
     for (int e = 0; e < NE; ++e) mo[e] = 0.0;
-    for (int x1 = lane; x1 < n1; x1 += 64) {
-        const double c = (double)(2 * x1 - (n1 - 1)) * rn;
-        double pw = (double)row[x1];
+    // eight loads of the row in flight per lane, then their moments
+    constexpr int kBatch = 8;
+    for (int base = 0; base < n1; base += 64 * kBatch) {
+        double px[kBatch];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) {
-            mo[e] += pw;
-            pw *= c;
+        for (int q = 0; q < kBatch; ++q) {
+            const int x1 = base + lane + 64 * q;
+            px[q] = x1 < n1 ? (double)row[x1] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            const double c = (double)(2 * (base + lane + 64 * q) - (n1 - 1)) * rn;
+            double pw = px[q];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                mo[e] += pw;
+                pw *= c;
+            }
+        }
+    }
+    // the wrapped columns of every shift lie within K1 of the row's ends
+    const bool staged = K1 <= kEdge;
+    if (staged) {
+        for (int t = lane; t < 2 * K1; t += 64) {
+            const int x1 = t < K1 ? t : n1 - 2 * K1 + t;
+            edge[wv][t] = (double)row[x1];
         }
     }
 #pragma unroll
@@ -97,7 +118,8 @@ __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, IoRef<const Tin> i
         for (int x1 = lo; x1 < hi; ++x1) {
             const double c = (double)(2 * x1 - (n1 - 1)) * rn;
             const double tor = (double)(2 * imod(x1 + d1, n1) - (n1 - 1)) * rn;
-            v += (double)row[x1] * ipow(c, ja) * (ipow(tor, jb) - ipow(c + sh, jb));
+            const double px = staged ? edge[wv][x1 < K1 ? x1 : x1 - n1 + 2 * K1] : (double)row[x1];
+            v += px * ipow(c, ja) * (ipow(tor, jb) - ipow(c + sh, jb));
         }
         vrow[(size_t)x0 * na * nb * nd + idx] = v;
     }

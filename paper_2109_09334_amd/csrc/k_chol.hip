@@ -18,34 +18,35 @@ constexpr int kFlagNonFinite = 2;
 constexpr int kFlagStall = 4;          // a bounded wait ran out (never expected)
 constexpr int kSolveSpin = 1 << 22;    // bound of every poll loop
 
-__global__ void clear_flag_kernel(int* flag) { *flag = 0; }
-
-__global__ void __launch_bounds__(256) diag_kernel(int n, const double* __restrict__ G,
-                                                    double* __restrict__ dsc, int* flag) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double gii = G[(size_t)i * n + i];
-    if (!isfinite(gii)) {
-        atomicOr(flag, kFlagNonFinite);
-        dsc[i] = 0.0;
-    } else if (!(gii > 0.0)) {
-        atomicOr(flag, kFlagNotSpd);
-        dsc[i] = 0.0;
-    } else {
-        dsc[i] = 1.0 / sqrt(gii);
-    }
+// A request's start: status flag and the solves' block flags cleared.
+__global__ void clear_flag_kernel(int* flag, int* tflag, int m) {
+    if (threadIdx.x == 0) *flag = 0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) tflag[i] = 0;
 }
 
-__global__ void __launch_bounds__(256) scale_kernel(int n, const double* __restrict__ G,
-                                                     const double* __restrict__ dsc,
-                                                     double* __restrict__ L, int* flag) {
+// Jacobi scaling, one block per row i: L_ij = d_i G_ij d_j (j <= i) with
+// d_j = 1/sqrt(G_jj) formed where it is used (0 for a bad diagonal, which
+// row j's own block reports).
+__device__ __forceinline__ double jacobi_d(double gjj) {
+    return (isfinite(gjj) && gjj > 0.0) ? 1.0 / sqrt(gjj) : 0.0;
+}
+
+__global__ void __launch_bounds__(256) jacobi_kernel(int n, const double* __restrict__ G,
+                                                      double* __restrict__ dsc,
+                                                      double* __restrict__ L, int* flag) {
     const int i = blockIdx.x;
-    const double di = dsc[i];
+    const double gii = G[(size_t)i * n + i];
+    const double di = jacobi_d(gii);
+    if (threadIdx.x == 0) {
+        dsc[i] = di;
+        if (!isfinite(gii)) atomicOr(flag, kFlagNonFinite);
+        else if (!(gii > 0.0)) atomicOr(flag, kFlagNotSpd);
+    }
     bool bad = false;
     for (int j = threadIdx.x; j <= i; j += blockDim.x) {
         const double gij = G[(size_t)i * n + j];
         bad |= !isfinite(gij);
-        L[(size_t)i * n + j] = di * gij * dsc[j];
+        L[(size_t)i * n + j] = di * gij * jacobi_d(G[(size_t)j * n + j]);
     }
     if (bad) atomicOr(flag, kFlagNonFinite);
 }
@@ -412,19 +413,18 @@ __global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__
 // ..., backward y_B first, then C = T-1, T-2, ...), so the sums do not depend
 // on timing; while it waits for block C it already holds that tile's row
 // slices and its W in registers. A block's result goes to tsv, then its
-// completion flag is set (release); readers poll the flag, then acquire.
+// completion flag is set to the solve's generation gen (release); readers
+// poll until the flag reaches gen, then acquire. The flags are cleared at
+// the start of each request (clear_flag_kernel) and every solve of the
+// request has the next generation, so no solve clears them itself.
 // Every wait is on a workgroup of lower index (dispatched earlier), and each
 // poll is bounded: past the bound the block sets kFlagStall and goes on.
-__global__ void tflag_clear_kernel(int* tflag, int m) {
-    for (int i = threadIdx.x; i < m; i += blockDim.x) tflag[i] = 0;
-}
-
-// Waits (thread 0, bounded) until *f is set, then makes the producer's
+// Waits (thread 0, bounded) until *f reaches gen, then makes the producer's
 // writes visible to the whole workgroup.
-__device__ __forceinline__ void wait_flag(const int* f, int* flag) {
+__device__ __forceinline__ void wait_flag(const int* f, int gen, int* flag) {
     if (threadIdx.x == 0) {
         int spins = 0;
-        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
             __builtin_amdgcn_s_sleep(2);
             if (++spins == kSolveSpin) {
                 atomicOr(flag, kFlagStall);
@@ -441,7 +441,8 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
                                                          const double* __restrict__ dsc,
                                                          const double* __restrict__ b,
                                                          double* __restrict__ coef, int accumulate,
-                                                         int* flag, double* tsv, int* tflag) {
+                                                         int* flag, double* tsv, int* tflag,
+                                                         int gen) {
     __shared__ double vsh[NBK];
     const int T = (n + NBK - 1) / NBK;
     const bool fwd = (int)blockIdx.x < T;
@@ -466,7 +467,7 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
         const double* row = L + (size_t)(r0 + min(i, nb - 1)) * n;
 #pragma unroll
         for (int q = 0; q < 16; ++q) m[q] = (i < nb && c0 + q < n) ? row[c0 + q] : 0.0;
-        wait_flag(fwd ? fdone + C : bdone + C, flag);
+        wait_flag(fwd ? fdone + C : bdone + C, gen, flag);
         if (threadIdx.x < NBK) {
             const int cc = C * NBK + threadIdx.x;
             vsh[threadIdx.x] = cc < n ? (fwd ? ys : zs)[cc] : 0.0;
@@ -478,7 +479,7 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
     }
     acc += __shfl_xor(acc, 1, 64);
     acc += __shfl_xor(acc, 2, 64);
-    if (!fwd) wait_flag(fdone + B, flag);   // y_B
+    if (!fwd) wait_flag(fdone + B, gen, flag);   // y_B
     if (p == 0) {
         const double rhs = i < nb ? (fwd ? dsc[r0 + i] * b[r0 + i] : ys[r0 + i]) : 0.0;
         vsh[i] = i < nb ? rhs - acc : 0.0;
@@ -502,11 +503,11 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0)
-        __hip_atomic_store(fwd ? fdone + B : bdone + B, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(fwd ? fdone + B : bdone + B, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-hipError_t launch_clear_flag(int* flag, hipStream_t st) {
-    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, st, flag);
+hipError_t launch_clear_flag(int* flag, int* tflag, int m, hipStream_t st) {
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(64), 0, st, flag, tflag, m);
     return hipGetLastError();
 }
 
@@ -514,8 +515,7 @@ hipError_t launch_jacobi(int n, const double* G, const double* h, double* L, dou
                          double* rhs, int* flag, hipStream_t st) {
     (void)h;
     (void)rhs;
-    hipLaunchKernelGGL(diag_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, G, dsc, flag);
-    hipLaunchKernelGGL(scale_kernel, dim3(n), dim3(256), 0, st, n, G, dsc, L, flag);
+    hipLaunchKernelGGL(jacobi_kernel, dim3(n), dim3(256), 0, st, n, G, dsc, L, flag);
     return hipGetLastError();
 }
 
@@ -534,11 +534,10 @@ hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* fl
 
 hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const double* dsc,
                              const double* rhs, double* coef, int accumulate, int* flag,
-                             double* tsv, int* tflag, hipStream_t st) {
+                             double* tsv, int* tflag, int gen, hipStream_t st) {
     const int T = (n + NBK - 1) / NBK;
-    hipLaunchKernelGGL(tflag_clear_kernel, dim3(1), dim3(64), 0, st, tflag, 2 * T);
     hipLaunchKernelGGL(trsv_flow_kernel, dim3(2 * T), dim3(256), 0, st, n, L, dinv, dsc, rhs, coef,
-                       accumulate, flag, tsv, tflag);
+                       accumulate, flag, tsv, tflag, gen);
     return hipGetLastError();
 }
 

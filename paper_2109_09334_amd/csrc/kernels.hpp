@@ -91,10 +91,13 @@ hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* fl
 // coef (+)= solution of G c = rhs (rhs is read only). tsv: scratch of 2 n
 // doubles, tflag: of 2 ceil(n/64) ints. flag gains kFlagStall if a block
 // of the solve waited past its bound (a broken dependency, never expected).
+// gen: this solve's generation within the request (1, 2, ...): the block
+// flags in tflag are cleared by launch_clear_flag at the request's start.
 hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const double* dsc,
                              const double* rhs, double* coef, int accumulate, int* flag,
-                             double* tsv, int* tflag, hipStream_t st);
-hipError_t launch_clear_flag(int* flag, hipStream_t st);
+                             double* tsv, int* tflag, int gen, hipStream_t st);
+// Status flag and the m solve block flags of a request cleared.
+hipError_t launch_clear_flag(int* flag, int* tflag, int m, hipStream_t st);
 // io[0..5] = the request's r_fit, s_fit, r, s, coef, d (slots kIo*).
 hipError_t launch_set_io(void** io, const void* rf, const void* sf, const void* r, const void* s,
                          double* coef, void* d, hipStream_t st);

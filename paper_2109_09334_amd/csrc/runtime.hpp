@@ -52,6 +52,8 @@ struct Workspace {
 };
 
 inline int poly_degree(const Geom& g) { return g.dk > g.db ? g.dk : g.db; }
+// Block flags of the triangular solves: forward and backward per 64 rows.
+inline int tflag_len(const Geom& g) { return 2 * ((g.nu + 63) / 64); }
 
 inline size_t carve(Workspace& w, const Geom& g, size_t cxb, size_t reb, char* base) {
     Carver c;
@@ -93,7 +95,7 @@ inline size_t carve(Workspace& w, const Geom& g, size_t cxb, size_t reb, char* b
     w.flag = c.take<int>(base, 64);
     w.io = c.take<void*>(base, kIoSlots);
     w.tsv = c.take<double>(base, 2 * (size_t)g.nu);
-    w.tflag = c.take<int>(base, 2 * ((g.nu + 63) / 64));
+    w.tflag = c.take<int>(base, tflag_len(g));
     return c.off + 256;
 }
 
