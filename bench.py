@@ -163,8 +163,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=8)
-    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--slots", type=int, default=8,
+                    help="engine slots of the closed-loop served runs (4096^2 batches, C4)")
+    ap.add_argument("--stream-slots", type=int, default=4,
+                    help="engine slots of the C5 stream (latency under load)")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--stars", type=int, default=40000)
     ap.add_argument("--stream-requests", type=int, default=200,
@@ -190,7 +193,7 @@ def main():
     # number of hardware queues (GPU_MAX_HW_QUEUES, 4 unless set) and streams
     # that share one run one after another, so ask for one per slot beside
     # the default stream's (read once, when HIP initialises: before torch).
-    hw_queues = max(8, args.slots + 2)
+    hw_queues = max(8, args.slots + args.stream_slots + 2)
     if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < hw_queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, hw_queues))
 
@@ -225,20 +228,23 @@ def main():
     dev = torch.device("cuda:0")
     R = torch.from_numpy(r_np).to(dev)
     S = torch.from_numpy(s_np).to(dev)
-    ctx = sf.Context(0)
+    ctx = sf.Context(0)           # direct per-stage calls
+    srv = sf.Context(0)           # closed-loop served runs: --slots
+    srv.engine_config(args.slots)
+    strm = sf.Context(0)          # the C5 stream: --stream-slots
+    strm.engine_config(args.stream_slots)
     pm = sf.Params(n, n, w, w, dk, db, 0, sf.MIXED, sf.F32)
     p64 = sf.Params(n, n, w, w, dk, db, 0, sf.FP64, sf.F32)
     nu = pm.num_unknowns
 
     def served(p, steps, warmup, batch):
-        ctx.engine_config(args.slots)
         outs = [(torch.empty(nu, dtype=torch.float64, device=dev),
                  torch.empty((n, n), dtype=torch.float32, device=dev)) for _ in range(batch)]
 
         def one_step():
-            ts = [ctx.submit(p, R, S, R, S, c, d) for (c, d) in outs]
+            ts = [srv.submit(p, R, S, R, S, c, d) for (c, d) in outs]
             for t in ts:
-                ctx.wait(t)
+                srv.wait(t)
 
         for _ in range(warmup):
             one_step()
@@ -288,15 +294,14 @@ def main():
 
     def mix_saturated(prec, count):
         """Closed-loop rate of the mix: every request submitted at once."""
-        ctx.engine_config(args.slots)
         rqs = mix_requests(count, seed=11)
         ps = [mix_params(rq, prec) for rq in rqs]
         outs = [take_out(p) for p in ps]
         t = time.perf_counter()
-        tk = [ctx.submit(p, *mix_pairs[rq["shape"]], *mix_pairs[rq["shape"]], *o)
+        tk = [strm.submit(p, *mix_pairs[rq["shape"]], *mix_pairs[rq["shape"]], *o)
               for p, rq, o in zip(ps, rqs, outs)]
         for x in tk:
-            ctx.wait(x)
+            strm.wait(x)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         for p, o in zip(ps, outs):
@@ -306,7 +311,6 @@ def main():
     def mix_stream(prec, rate, count, warm):
         """Poisson arrivals at `rate`; latency = completion - arrival, host
         clock, queueing included; the first `warm` requests are not counted."""
-        ctx.engine_config(args.slots)
         rqs = mix_requests(count + warm, seed=7)
         arrivals = datagen.poisson_arrivals(count + warm, rate, seed=7)
         lat, pending = [], {}
@@ -319,11 +323,11 @@ def main():
                 p = mix_params(rq, prec)
                 o = take_out(p)
                 R_, S_ = mix_pairs[rq["shape"]]
-                tk = ctx.submit(p, R_, S_, R_, S_, *o)
+                tk = strm.submit(p, R_, S_, R_, S_, *o)
                 pending[tk] = (arrivals[i], i, p, o)
                 i += 1
             for tk in list(pending):
-                if ctx.poll(tk) == sf.OK:
+                if strm.poll(tk) == sf.OK:
                     arr, k, p, o = pending.pop(tk)
                     if k >= warm:
                         lat.append(time.perf_counter() - t_start - arr)
@@ -336,7 +340,6 @@ def main():
     def c4_batch():
         """C4: 64 ragged pairs (512^2 .. 2048x4096, w = 5, DK = DB = 1) served
         as one batch through the engine (mixed form)."""
-        ctx.engine_config(args.slots)
         pairs = {}
         for shp in datagen.BATCH_SHAPES:
             pr = cached_pair(f"c4_{shp[0]}x{shp[1]}",
@@ -349,9 +352,9 @@ def main():
                  torch.empty((p.n0, p.n1), dtype=torch.float32, device=dev)) for p in ps]
 
         def once():
-            tk = [ctx.submit(p, *pairs[s], *pairs[s], *o) for p, s, o in zip(ps, picks, outs)]
+            tk = [srv.submit(p, *pairs[s], *pairs[s], *o) for p, s, o in zip(ps, picks, outs)]
             for x in tk:
-                ctx.wait(x)
+                srv.wait(x)
             torch.cuda.synchronize()
 
         once()   # plans and workspaces
@@ -461,6 +464,7 @@ def main():
                                f"15x15 kernel (w=7), DK=2, DB=2, {nu} unknowns",
                    "precision": "mixed: FP32 FFTs/products, FP64 lags/assembly/Cholesky/refinement",
                    "batch_per_step": args.batch, "engine_slots": args.slots,
+                   "stream_engine_slots": args.stream_slots,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "p50_latency_ms": stream["mixed"]["loads"]["0.8"]["p50_ms"] if stream else None,
         "p99_latency_ms": stream["mixed"]["loads"]["0.8"]["p99_ms"] if stream else None,
