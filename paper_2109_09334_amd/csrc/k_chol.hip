@@ -57,7 +57,19 @@ __global__ void __launch_bounds__(256) jacobi_kernel(int n, const double* __rest
 // I (v_mfma_f64_16x16x4: lane l holds A[l%16][l/16], B[l/16][l%16], and
 // result row l/16 + 4 q, column l%16 in register q).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
-constexpr int kStepThreads = 512;   // eight waves per panel / tile workgroup
+constexpr int kStepThreads = 512;   // threads per panel / tile workgroup
+// The 4 x 4 blocks (16 x 16) of a 64 x 64 matrix-core product over the
+// waves: with eight waves, column strip w % 4 and row blocks 2 (w / 4) + {0,
+// 1}; with four, strip w and all row blocks; with two, strips 2w, 2w + 1.
+constexpr int kStepWaves = kStepThreads / 64;
+constexpr int kBlocksPerStrip = kStepWaves >= 4 ? 16 / kStepWaves : 4;
+constexpr int kStripsPerWave = kStepWaves >= 4 ? 1 : 4 / kStepWaves;
+__device__ __forceinline__ int strip_of(int wv, int t) {
+    return kStepWaves >= 4 ? (wv & 3) : kStripsPerWave * wv + t;
+}
+__device__ __forceinline__ int rowblock0_of(int wv) {
+    return kStepWaves >= 4 ? kBlocksPerStrip * (wv >> 2) : 0;
+}
 
 // Row blocks I0 .. I0+NI-1 of the strip s:
 //   acc[I] = sum_c P[16 (I0 + I) + r][c] Q[16 s + t][c]   (r, t < 16).
@@ -107,20 +119,22 @@ __device__ __forceinline__ void tile_update(int n, double* __restrict__ L, int k
                                             double (*PI)[NBK + 1], double (*PJ)[NBK + 1]) {
     const int ni = min(NBK, n - i0), nj = min(NBK, n - j0);
     stage_panels(L, n, kp, i0, ni, j0, nj, PI, PJ);
-    // eight waves: column strip wv % 4, row blocks 2 (wv / 4) and 2 (wv / 4) + 1
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int I0 = 2 * (wv >> 2), sc = wv & 3;
-    dbl4 acc[2];
-    panel_mfma<2>(PI, PJ, I0, sc, lane, acc);
-    const int jc = 16 * sc + (lane & 15);
 #pragma unroll
-    for (int I = 0; I < 2; ++I)
+    for (int t = 0; t < kStripsPerWave; ++t) {
+        const int sc = strip_of(wv, t), I0 = rowblock0_of(wv);
+        dbl4 acc[kBlocksPerStrip];
+        panel_mfma<kBlocksPerStrip>(PI, PJ, I0, sc, lane, acc);
+        const int jc = 16 * sc + (lane & 15);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = 16 * (I0 + I) + (lane >> 4) + 4 * q;
-            if (i < ni && jc < nj && !(i0 == j0 && jc > i))
-                L[(size_t)(i0 + i) * n + j0 + jc] -= acc[I][q];
-        }
+        for (int I = 0; I < kBlocksPerStrip; ++I)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * (I0 + I) + (lane >> 4) + 4 * q;
+                if (i < ni && jc < nj && !(i0 == j0 && jc > i))
+                    L[(size_t)(i0 + i) * n + j0 + jc] -= acc[I][q];
+            }
+    }
 }
 
 // Step k of the right-looking factorisation, with the trailing update of
@@ -183,24 +197,29 @@ __global__ void __launch_bounds__(kStepThreads) chol_step_kernel(int n, double* 
         // panel k-1 (64 full columns at kp) onto D and onto this row block
         const int kp = kb - NBK;
         stage_panels(L, n, kp, r0, nr, kb, nb, PI, PJ);
-        // the update on the matrix cores (wave: column strip wv % 4, row
-        // blocks 2 (wv / 4) + {0, 1}); the strips go through LDS into the
+        // the update on the matrix cores (blocks over the waves as in
+        // strip_of / rowblock0_of); the strips go through LDS into the
         // factor's register tiles
         const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        const int I0 = 2 * (wv >> 2), sc = wv & 3;
-        dbl4 ud[2], ux[2];
-        panel_mfma<2>(PJ, PJ, I0, sc, lane, ud);
-        panel_mfma<2>(PI, PJ, I0, sc, lane, ux);
+        dbl4 ud[kStripsPerWave][kBlocksPerStrip], ux[kStripsPerWave][kBlocksPerStrip];
+#pragma unroll
+        for (int t = 0; t < kStripsPerWave; ++t) {
+            panel_mfma<kBlocksPerStrip>(PJ, PJ, rowblock0_of(wv), strip_of(wv, t), lane, ud[t]);
+            panel_mfma<kBlocksPerStrip>(PI, PJ, rowblock0_of(wv), strip_of(wv, t), lane, ux[t]);
+        }
         __syncthreads();   // every wave is done reading the panels
-        const int jc = 16 * sc + (lane & 15);
 #pragma unroll
-        for (int I = 0; I < 2; ++I)
+        for (int t = 0; t < kStripsPerWave; ++t) {
+            const int jc = 16 * strip_of(wv, t) + (lane & 15);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = 16 * (I0 + I) + (lane >> 4) + 4 * q;
-                PJ[i][jc] = ud[I][q];
-                PI[i][jc] = ux[I][q];
-            }
+            for (int I = 0; I < kBlocksPerStrip; ++I)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = 16 * (rowblock0_of(wv) + I) + (lane >> 4) + 4 * q;
+                    PJ[i][jc] = ud[t][I][q];
+                    PI[i][jc] = ux[t][I][q];
+                }
+        }
         __syncthreads();
 #pragma unroll
         for (int a = 0; a < RA; ++a)
