@@ -6,7 +6,8 @@ A step is one batch of `--batch` independent requests (build the normal
 equations, solve, refine, subtract) served concurrently by the library's
 engine; inputs are resident in HBM before the timed region. The JSON line
 reports the mixed-precision served form's pairs/s (value) and, beside it,
-the plain FP64 form, p50/p99 latency of a Poisson stream, per-stage times
+the plain FP64 form, p50/p99 latency of a Poisson stream of the C5 size mix
+(2048^2 / 4096^2 / 6144^2), the C4 ragged batch, per-stage times
 (HIP events), the roofline of the dominant kernel and the FP64 CPU oracle
 timed on a bounded crop of the same workload.
 

@@ -4,10 +4,11 @@
 // matrix D G D is factorised by a blocked right-looking Cholesky (64-wide
 // panels: the diagonal block is factorised and the panel below it solved
 // against that factor in one register-tiled pass; each panel's update of the
-// trailing lower triangle, in 64x64 FP64 tiles, runs in the next panel's
-// launch), then L y = D b and L^T z = y are solved with 64-row blocks and
-// c = D z. A non-positive or non-finite pivot sets a device flag instead of
-// stopping; the host reports it and the coefficients are set to NaN.
+// trailing lower triangle, in 64x64 FP64 tiles on the matrix cores, runs in
+// the next panel's launch), then L y = D b and L^T z = y are solved as a
+// dataflow of 64-row blocks across workgroups and c = D z. A non-positive or
+// non-finite pivot sets a device flag instead of stopping; the host reports
+// it and the coefficients are set to NaN.
 #include "kernels.hpp"
 
 namespace sfft {
