@@ -55,9 +55,8 @@ template <typename Tin, int NE>
 __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, IoRef<const Tin> imgr, int da,
                                                       int dbb, int K1, double* __restrict__ vrow) {
     const Tin* __restrict__ img = imgr.get();
-    constexpr int kEdge = 64;   // edge pixels kept in LDS per side (K1 <= kEdge)
     __shared__ double mom[4][kMaxMom];
-    __shared__ double edge[4][2 * kEdge];
+    __shared__ double esum[4][2][NE][kPolyRowMaxLag + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int x0 = blockIdx.x * 4 + wv;
     if (x0 >= g.n0) return;   // wave-level work only below
@@ -65,18 +64,25 @@ __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, IoRef<const Tin> i
     const Tin* row = img + (size_t)x0 * n1;
     // c1(x1) = (2 x1 - (N1 - 1)) / (N1 - 1) with the division as a product
     const double rn = 1.0 / (double)(n1 - 1);
+    // edge pixel of this lane: column k of the left end (lane k < 32) or
+    // of the right end (lane 32 + k), for k < K1; loaded ahead of the row
+    const int ek = lane & 31, eside = lane >> 5;
+    const int ex1 = eside ? n1 - 1 - ek : ek;
+    const double epx = ek < K1 ? (double)row[min(max(ex1, 0), n1 - 1)] : 0.0;
     double mo[NE];
 #pragma unroll
     for (int e = 0; e < NE; ++e) mo[e] = 0.0;
-    // eight loads of the row in flight per lane, then their moments
+    // eight loads of the row in flight per lane, then their moments; the
+    // loads past the row's end read its last pixel (clamped index, no
+    // branch around the load) and are then dropped
     constexpr int kBatch = 8;
     for (int base = 0; base < n1; base += 64 * kBatch) {
+        Tin ld[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) ld[q] = row[min(base + lane + 64 * q, n1 - 1)];
         double px[kBatch];
 #pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-            const int x1 = base + lane + 64 * q;
-            px[q] = x1 < n1 ? (double)row[x1] : 0.0;
-        }
+        for (int q = 0; q < kBatch; ++q) px[q] = base + lane + 64 * q < n1 ? (double)ld[q] : 0.0;
 #pragma unroll
         for (int q = 0; q < kBatch; ++q) {
             const double c = (double)(2 * (base + lane + 64 * q) - (n1 - 1)) * rn;
@@ -88,12 +94,28 @@ __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, IoRef<const Tin> i
             }
         }
     }
-    // the wrapped columns of every shift lie within K1 of the row's ends
-    const bool staged = K1 <= kEdge;
-    if (staged) {
-        for (int t = lane; t < 2 * K1; t += 64) {
-            const int x1 = t < K1 ? t : n1 - 2 * K1 + t;
-            edge[wv][t] = (double)row[x1];
+    // The wrapped columns of shift d1 are the |d1| columns at one end of
+    // the row (the right end for d1 > 0), where c1 of the wrapped column is
+    // u - Delta with u = c1(x1) + 2 d1/(N1-1) and Delta = +-2 N1/(N1-1).
+    // (u - Delta)^jb - u^jb expands in powers of Delta, u and then of
+    // c1(x1), so the correction needs only the edge sums
+    //   E_e(side, k) = sum of img c1^e over the k columns nearest that end,
+    // formed once per row as prefix sums over the edge lanes.
+    {
+        const double cc = (double)(2 * ex1 - (n1 - 1)) * rn;
+        double pw = epx;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            // inclusive prefix sum over the 32 lanes of this side
+            double s = pw;
+#pragma unroll
+            for (int off = 1; off < 32; off <<= 1) {
+                const double t = __shfl_up(s, off, 32);
+                if (ek >= off) s += t;
+            }
+            esum[wv][eside][e][ek + 1] = s;
+            if (ek == 0) esum[wv][eside][e][0] = 0.0;
+            pw *= cc;
         }
     }
 #pragma unroll
@@ -114,12 +136,18 @@ __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, IoRef<const Tin> i
         const double sh = del * (double)d1;
         double v = 0.0;
         for (int r = 0; r <= jb; ++r) v += binom(jb, r) * ipow(sh, jb - r) * mom[wv][ja + r];
-        const int lo = d1 > 0 ? n1 - d1 : 0, hi = d1 > 0 ? n1 : -d1;
-        for (int x1 = lo; x1 < hi; ++x1) {
-            const double c = (double)(2 * x1 - (n1 - 1)) * rn;
-            const double tor = (double)(2 * imod(x1 + d1, n1) - (n1 - 1)) * rn;
-            const double px = staged ? edge[wv][x1 < K1 ? x1 : x1 - n1 + 2 * K1] : (double)row[x1];
-            v += px * ipow(c, ja) * (ipow(tor, jb) - ipow(c + sh, jb));
+        if (d1 != 0 && jb > 0) {
+            const int side = d1 > 0 ? 1 : 0, k = d1 > 0 ? d1 : -d1;
+            const double mdelta = (d1 > 0 ? -2.0 : 2.0) * (double)n1 * rn;   // -Delta
+            double corr = 0.0, mdt = 1.0;
+            for (int t = 1; t <= jb; ++t) {
+                mdt *= mdelta;
+                double inner = 0.0;
+                for (int q = 0; q <= jb - t; ++q)
+                    inner += binom(jb - t, q) * ipow(sh, jb - t - q) * esum[wv][side][ja + q][k];
+                corr += binom(jb, t) * mdt * inner;
+            }
+            v += corr;
         }
         vrow[(size_t)x0 * na * nb * nd + idx] = v;
     }
@@ -357,6 +385,7 @@ __global__ void __launch_bounds__(256) lagfix_kernel(Geom g, int mode, const dou
 template <typename Tin>
 hipError_t launch_polyrow(const Geom& g, IoRef<const Tin> img, int da, int dbb, int K1,
                           double* vrow, hipStream_t st) {
+    if (K1 < 0 || K1 > kPolyRowMaxLag || K1 >= g.n1) return hipErrorInvalidValue;
     const dim3 grid((g.n0 + 3) / 4), block(256);
     switch (da + dbb + 1) {
 #define SFFT_POLYROW(NE)                                                                        \

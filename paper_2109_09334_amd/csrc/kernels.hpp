@@ -55,6 +55,8 @@ hipError_t launch_lagrow(const Geom& g, int p0, int p1, const cx<T>* Cl, const d
                          double* omega, double* theta, hipStream_t st);
 
 // FP64 polynomial-correlation tables and pedestal corrections (k_background).
+// polyrow: row moments for axis-1 shifts |d1| <= K1 (K1 <= kPolyRowMaxLag, < N1).
+constexpr int kPolyRowMaxLag = 32;
 template <typename Tin>
 hipError_t launch_polyrow(const Geom& g, IoRef<const Tin> img, int da, int dbb, int K1,
                           double* vrow, hipStream_t st);
