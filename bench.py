@@ -81,8 +81,11 @@ def stage_work(g, stage, s_cx):
     nu = P * L * L + Q
     fft = lambda N: 5.0 * N * math.log2(N)
     if stage == "background":      # FP64 poly-correlation tables: one pass over R and S
+        # per pixel, the row power sums c1^e (e <= DK + D for R, e <= D for S,
+        # D = max(DK, DB)); the shift tables then come from per-row moments
+        dm = max(dk, db)
         by = 2 * 4 * n
-        fl = n * 2.0 * (2 * dk + 2 + (dk + 1) * (dk + 1) * (4 * w + 1))
+        fl = n * 2.0 * ((dk + dm + 1) + (dm + 1))
     elif stage == "rowfwd":
         by = 2 * 4 * n + nr * n0 * H * s_cx
         fl = n0 * math.ceil(nr / 2) * fft(n1)
