@@ -165,18 +165,15 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
     if (act) {
         const cx<T>* A = Dt + (size_t)xa * g.hp;
         const cx<T>* B = Dt + (size_t)xb * g.hp;
+        // bins past the half spectrum are the conjugates of their mirrors:
+        // every load is issued unconditionally from the folded index
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) {
             const int m = lt + e * lp.tl;
-            cx<T> a, b;
-            if (m < g.h) {
-                a = A[m];
-                b = B[m];
-                if (m == 0 || 2 * m == n1) { a.im = T(0); b.im = T(0); }
-            } else {
-                a = cconj(A[n1 - m]);
-                b = cconj(B[n1 - m]);
-            }
+            const int mf = m < g.h ? m : n1 - m;
+            cx<T> a = A[mf], b = B[mf];
+            if (m >= g.h) { a.im = -a.im; b.im = -b.im; }
+            if (m == 0 || 2 * m == n1) { a.im = T(0); b.im = T(0); }
             v[e] = mk(a.re - b.im, a.im + b.re);
         }
     } else {
@@ -195,21 +192,40 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
         const double* rb = (xb < w0 || xb >= n0 - w0)
                                ? sky + (size_t)(R + 1 + (xb < w0 ? xb : xb - n0 + 2 * w0)) * n1
                                : nullptr;
+        // four elements at a time, the table rows of each power loaded
+        // together (one batch of loads in flight per power)
+        constexpr int kChunk = 4;
+        static_assert(kElemsPerThread % kChunk == 0, "chunked sky terms");
 #pragma unroll
-        for (int e = 0; e < kElemsPerThread; ++e) {
-            const int x1 = lt + e * lp.tl;
-            double ba = 0.0, bb = 0.0, pa = 1.0, pb = 1.0;
+        for (int e0 = 0; e0 < kElemsPerThread; e0 += kChunk) {
+            double ba[kChunk], bb[kChunk];
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) ba[q] = bb[q] = 0.0;
+            double pa = 1.0, pb = 1.0;
             for (int r = 0; r <= R; ++r) {
-                const double y = sky[(size_t)r * n1 + x1];
-                ba += pa * y;
-                bb += pb * y;
+                double y[kChunk];
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) y[q] = sky[(size_t)r * n1 + lt + (e0 + q) * lp.tl];
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) {
+                    ba[q] += pa * y[q];
+                    bb[q] += pb * y[q];
+                }
                 pa *= ca;
                 pb *= cb;
             }
-            if (ra) ba = ra[x1];
-            if (rb) bb = rb[x1];
-            d[(size_t)xa * n1 + x1] = Tout((double)v[e].re * inv - ba);
-            d[(size_t)xb * n1 + x1] = Tout((double)v[e].im * inv - bb);
+            if (ra)
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) ba[q] = ra[lt + (e0 + q) * lp.tl];
+            if (rb)
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) bb[q] = rb[lt + (e0 + q) * lp.tl];
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) {
+                const int x1 = lt + (e0 + q) * lp.tl;
+                d[(size_t)xa * n1 + x1] = Tout((double)v[e0 + q].re * inv - ba[q]);
+                d[(size_t)xb * n1 + x1] = Tout((double)v[e0 + q].im * inv - bb[q]);
+            }
         }
     }
 }
