@@ -144,6 +144,16 @@ __host__ __device__ __forceinline__ T ipow(T b, int e) {
     return r;
 }
 
+// b^e for 0 <= e <= MaxE as a fixed chain of MaxE selected products: the same
+// products in the same order as ipow, without a loop on a runtime count.
+template <int MaxE, typename T>
+__host__ __device__ __forceinline__ T ipow_upto(T b, int e) {
+    T r = T(1);
+#pragma unroll
+    for (int k = 0; k < MaxE; ++k) r = k < e ? r * b : r;
+    return r;
+}
+
 // Binomial coefficient C(n, k) as a double (small n).
 __host__ __device__ __forceinline__ double binom(int n, int k) {
     double r = 1.0;

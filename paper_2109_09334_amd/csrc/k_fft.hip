@@ -48,12 +48,19 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
             const int ea = src.pow[ia], eb = hasb ? src.pow[ib] : 0;
             const double qa = src.ped[ia] >= 0 ? ped[src.ped[ia]] : 0.0;
             const double qb = hasb && src.ped[ib] >= 0 ? ped[src.ped[ib]] : 0.0;
+            // both rows loaded unconditionally (pb is a valid row when the
+            // pair has no second source), then the weights applied
+            Tin la[kElemsPerThread], lb[kElemsPerThread];
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e) {
-                const int x1 = lt + e * lp.tl;
-                const T c = coord<T>(x1, n1);
-                const T va = ipow(c, ea) * T((double)pa[x1] - qa);
-                const T vb = hasb ? ipow(c, eb) * T((double)pb[x1] - qb) : T(0);
+                la[e] = pa[lt + e * lp.tl];
+                lb[e] = pb[lt + e * lp.tl];
+            }
+#pragma unroll
+            for (int e = 0; e < kElemsPerThread; ++e) {
+                const T c = coord<T>(lt + e * lp.tl, n1);
+                const T va = ipow_upto<kMaxDegree>(c, ea) * T((double)la[e] - qa);
+                const T vb = hasb ? ipow_upto<kMaxDegree>(c, eb) * T((double)lb[e] - qb) : T(0);
                 v[e] = mk(va, vb);
             }
         } else {
@@ -264,6 +271,9 @@ template <typename T, typename Tin>
 hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& src,
                          IoRef<const Tin> img0, IoRef<const Tin> img1, const double* ped, cx<T>* Z,
                          const cx<T>* twt, hipStream_t st) {
+    if (src.n < 1 || src.n > kMaxSrc) return hipErrorInvalidValue;
+    for (int s = 0; s < src.n; ++s)
+        if (src.pow[s] < 0 || src.pow[s] > kMaxDegree) return hipErrorInvalidValue;
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     dim3 grid((g.n0 + lp.lpw - 1) / lp.lpw);
     return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
