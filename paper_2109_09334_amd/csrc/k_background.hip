@@ -127,29 +127,48 @@ __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, IoRef<const Tin> i
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // Shift d1 across the lanes, (ja, jb) uniform over the wave: the powers
+    // of the shift and of -Delta are formed once per lane by the same
+    // repeated products as ipow, and the binomial sums unroll on static
+    // bounds (jb <= kMaxDegree).
     const int na = da + 1, nb = dbb + 1, nd = 2 * K1 + 1;
     const double del = 2.0 / (double)(n1 - 1);
-    for (int idx = lane; idx < na * nb * nd; idx += 64) {
-        const int ja = idx / (nb * nd);
-        const int jb = (idx / nd) % nb;
-        const int d1 = idx % nd - K1;
+    double* out = vrow + (size_t)x0 * na * nb * nd;
+    for (int i = lane; i < nd; i += 64) {
+        const int d1 = i - K1;
+        const int side = d1 > 0 ? 1 : 0, k = d1 > 0 ? d1 : -d1;
         const double sh = del * (double)d1;
-        double v = 0.0;
-        for (int r = 0; r <= jb; ++r) v += binom(jb, r) * ipow(sh, jb - r) * mom[wv][ja + r];
-        if (d1 != 0 && jb > 0) {
-            const int side = d1 > 0 ? 1 : 0, k = d1 > 0 ? d1 : -d1;
-            const double mdelta = (d1 > 0 ? -2.0 : 2.0) * (double)n1 * rn;   // -Delta
-            double corr = 0.0, mdt = 1.0;
-            for (int t = 1; t <= jb; ++t) {
-                mdt *= mdelta;
-                double inner = 0.0;
-                for (int q = 0; q <= jb - t; ++q)
-                    inner += binom(jb - t, q) * ipow(sh, jb - t - q) * esum[wv][side][ja + q][k];
-                corr += binom(jb, t) * mdt * inner;
-            }
-            v += corr;
+        const double mdelta = (d1 > 0 ? -2.0 : 2.0) * (double)n1 * rn;   // -Delta
+        double shp[kMaxDegree + 1], mdp[kMaxDegree + 1];
+        shp[0] = 1.0;
+        mdp[0] = 1.0;
+#pragma unroll
+        for (int q = 1; q <= kMaxDegree; ++q) {
+            shp[q] = shp[q - 1] * sh;
+            mdp[q] = mdp[q - 1] * mdelta;
         }
-        vrow[(size_t)x0 * na * nb * nd + idx] = v;
+        for (int ja = 0; ja < na; ++ja) {
+#pragma unroll
+            for (int jb = 0; jb <= kMaxDegree; ++jb) {
+                if (jb > dbb) break;
+                double v = 0.0;
+#pragma unroll
+                for (int r = 0; r <= jb; ++r) v += binom(jb, r) * shp[jb - r] * mom[wv][ja + r];
+                if (d1 != 0 && jb > 0) {
+                    double corr = 0.0;
+#pragma unroll
+                    for (int t = 1; t <= jb; ++t) {
+                        double inner = 0.0;
+#pragma unroll
+                        for (int q = 0; q <= jb - t; ++q)
+                            inner += binom(jb - t, q) * shp[jb - t - q] * esum[wv][side][ja + q][k];
+                        corr += binom(jb, t) * mdp[t] * inner;
+                    }
+                    v += corr;
+                }
+                out[(ja * nb + jb) * nd + i] = v;
+            }
+        }
     }
 }
 
@@ -386,6 +405,7 @@ template <typename Tin>
 hipError_t launch_polyrow(const Geom& g, IoRef<const Tin> img, int da, int dbb, int K1,
                           double* vrow, hipStream_t st) {
     if (K1 < 0 || K1 > kPolyRowMaxLag || K1 >= g.n1) return hipErrorInvalidValue;
+    if (da < 0 || dbb < 0 || dbb > kMaxDegree || da + dbb + 1 > kMaxMom) return hipErrorInvalidValue;
     const dim3 grid((g.n0 + 3) / 4), block(256);
     switch (da + dbb + 1) {
 #define SFFT_POLYROW(NE)                                                                        \
