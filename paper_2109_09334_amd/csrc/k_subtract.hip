@@ -114,20 +114,28 @@ __global__ void __launch_bounds__(256) sky_stamps_kernel(Geom g, const double* _
 }
 
 constexpr int kSkyThreads = 64;
+constexpr int kMaxTerms = (kMaxDegree + 1) * (kMaxDegree + 2) / 2;   // P at DK = kMaxDegree
+constexpr int kMaxHalfWidth = 16;                                      // largest w0, w1
 
 __global__ void __launch_bounds__(kSkyThreads) sky_kernel(Geom g, const double* __restrict__ kap1,
                                                           const double* __restrict__ bcoef,
                                                           const double* __restrict__ ped,
                                                           double* __restrict__ sky) {
+    // this rho's 1-D stamps, P x L1 doubles, staged once per block
+    __shared__ double kr[kMaxTerms * (2 * kMaxHalfWidth + 1)];
     const int x1 = blockIdx.x * kSkyThreads + threadIdx.x;
     const int rho = blockIdx.y;
-    if (x1 >= g.n1) return;
     const int n1 = g.n1, w1 = g.w1;
     const int R = max(g.dk, g.db);
     const double cR = ped ? ped[0] : 0.0, cS = ped ? ped[1] : 0.0;
+    if (cR != 0.0) {
+        const double* src = kap1 + (size_t)rho * g.P * g.L1;
+        for (int t = threadIdx.x; t < g.P * g.L1; t += blockDim.x) kr[t] = src[t];
+        __syncthreads();
+    }
+    if (x1 >= g.n1) return;
     double v = 0.0;
     if (cR != 0.0) {
-        const double* kr = kap1 + (size_t)rho * g.P * g.L1;
         for (int b = -w1; b <= w1; ++b) {
             const double c = coord<double>(imod(x1 - b, n1), n1);
             double pw[kMaxDegree + 1];
@@ -386,7 +394,8 @@ hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<
 
 hipError_t launch_sky(const Geom& g, const double* kap, const double* bcoef, const double* ped,
                       double* kap1, double* sky, hipStream_t st) {
-    if (g.dk > kMaxDegree || g.db > kMaxDegree) return hipErrorInvalidValue;
+    if (g.dk > kMaxDegree || g.db > kMaxDegree || g.w1 > kMaxHalfWidth || g.P > kMaxTerms)
+        return hipErrorInvalidValue;
     const int nrho = max(g.dk, g.db) + 1 + 2 * g.w0;
     if (ped) hipLaunchKernelGGL(sky_stamps_kernel, dim3(nrho), dim3(256), 0, st, g, kap, kap1);
     hipLaunchKernelGGL(sky_kernel, dim3((g.n1 + kSkyThreads - 1) / kSkyThreads, nrho),
