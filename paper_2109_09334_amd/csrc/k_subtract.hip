@@ -286,8 +286,9 @@ __global__ void __launch_bounds__(256) stencil_reg_kernel(Geom g, const cx<T>* _
 #pragma unroll
     for (int o = 0; o < NO; ++o)
         acc[o] = x0b + o < n0 ? Z[(size_t)zs * plane + (size_t)(x0b + o) * g.hp + m] : mk(T(0), T(0));
-    // Horner over the full degree DK with the stamp terms i > DK - j set to
-    // zero once per tap (no per-output selects).
+    // Horner over degree DK - j in c0 of the source row. The j loop stays a
+    // runtime loop (one set of source rows live at a time); its body is
+    // compiled once per degree and picked by a switch.
 #pragma unroll 1
     for (int j = 0; j <= DK; ++j) {
         const cx<T>* Zj = Z + (size_t)j * plane + m;
@@ -297,31 +298,33 @@ __global__ void __launch_bounds__(256) stencil_reg_kernel(Geom g, const cx<T>* _
         cx<T> z[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) z[s] = Zj[(size_t)(xs[s] + oz) * g.hp];
-        const int ni = DK - j;
+        auto taps = [&](auto ni_c) {
+            constexpr int NI = decltype(ni_c)::value;
 #pragma unroll
-        for (int a = 0; a < L0; ++a) {   // tap a0 = a - W0
-            cx<T> kt[DK + 1];
+            for (int a = 0; a < L0; ++a) {   // tap a0 = a - W0
+                cx<T> kt[NI + 1];
 #pragma unroll
-            for (int i = 0; i <= DK; ++i) {
-                const cx<T> v = ktl[term_index(DK, i <= ni ? i : 0, j) * L0 + a][mc];
-                kt[i] = i <= ni ? v : mk(T(0), T(0));
+                for (int i = 0; i <= NI; ++i) kt[i] = ktl[term_index(DK, i, DK - NI) * L0 + a][mc];
+#pragma unroll
+                for (int o = 0; o < NO; ++o) {
+                    const int s = o + 2 * W0 - a;   // source row x0 - a0
+                    const T c = cs[s];
+                    cx<T> poly = kt[NI];
+#pragma unroll
+                    for (int i = NI - 1; i >= 0; --i)
+                        poly = mk(fmat(poly.re, c, kt[i].re), fmat(poly.im, c, kt[i].im));
+                    // the tap's term first, so that each tap rounds once at
+                    // the accumulator's magnitude (|Z_S|, far above the result)
+                    const cx<T> t = mk(fmat(poly.re, z[s].re, -poly.im * z[s].im),
+                                       fmat(poly.re, z[s].im, poly.im * z[s].re));
+                    acc[o] = acc[o] - t;
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
-#pragma unroll
-            for (int o = 0; o < NO; ++o) {
-                const int s = o + 2 * W0 - a;   // source row x0 - a0
-                const T c = cs[s];
-                cx<T> poly = kt[DK];
-#pragma unroll
-                for (int i = DK - 1; i >= 0; --i)
-                    poly = mk(fmat(poly.re, c, kt[i].re), fmat(poly.im, c, kt[i].im));
-                // the tap's term first, so that each tap rounds once at the
-                // accumulator's magnitude (|Z_S|, far above the result)
-                const cx<T> t = mk(fmat(poly.re, z[s].re, -poly.im * z[s].im),
-                                   fmat(poly.re, z[s].im, poly.im * z[s].re));
-                acc[o] = acc[o] - t;
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
+        };
+        static_for<0, DK + 1>([&](auto ni_c) {
+            if (DK - j == decltype(ni_c)::value) taps(ni_c);
+        });
     }
 #pragma unroll
     for (int o = 0; o < NO; ++o)
