@@ -183,6 +183,8 @@ __device__ __forceinline__ int lag_twiddle_index(int n0, int j, int tb, int r) {
     const int mres = tb & 15;
     const int t = tb - mres + r + (r < mres ? 16 : 0);
     int idx = j * t;
+    // a power-of-two N0 reduces the (possibly negative) product with a mask
+    if ((n0 & (n0 - 1)) == 0) return idx & (n0 - 1);
 #pragma unroll
     for (int c3 = 0; c3 < 3; ++c3) idx += idx < 0 ? n0 : 0;
 #pragma unroll
