@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(256) stencil_reg_kernel(Geom g, const cx<T>* _
 template <typename T, int DK, int W0>
 static hipError_t launch_stencil_reg(const Geom& g, const cx<T>* Z, int zs, const cx<T>* Kt,
                                      cx<T>* Dt, hipStream_t st) {
-    constexpr int NO = 8;
+    constexpr int NO = 16;
     dim3 grid((g.h + 63) / 64, (g.n0 + 4 * NO - 1) / (4 * NO));
     hipLaunchKernelGGL((stencil_reg_kernel<T, DK, W0, NO>), grid, dim3(256), 0, st, g, Z, zs, Kt, Dt);
     return hipGetLastError();
