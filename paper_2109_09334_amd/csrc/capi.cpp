@@ -436,6 +436,7 @@ static hipError_t refine(Plan& pl, double* coef, int gen, hipStream_t st) {
     src.img[0] = 0;
     src.out[0] = g.nr;
     src.ped[0] = -1;
+    src.rowpair = 1;   // D's rows two to a line
     if (!e) e = launch_rowfwd<T, T>(g, pl.lp1, src, dfit, dfit, w.ped, cxp<T>(w.Z), cxp<T>(pl.t1.twt), st);
     ColJobs jobs{};
     jobs.narr = 1;

@@ -29,22 +29,25 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
     const Tin* __restrict__ img0 = img0r.get();
     const Tin* __restrict__ img1 = img1r.get();
     const int line = threadIdx.x / lp.tl, lt0 = threadIdx.x - line * lp.tl;
+    // the line packs two sources of one image row, or (rowpair) one source
+    // on the image rows xa = 2 r and xb = 2 r + 1
     const int row = blockIdx.x * lp.lpw + line;
-    const bool act = row < g.n0;
+    const int xa = src.rowpair ? 2 * row : row, xb = src.rowpair ? 2 * row + 1 : row;
+    const bool act = xb < g.n0;
     const int n1 = g.n1;
     cx<T>* buf = lds + line * line_lds_elems(n1);
     const int npk = (src.n + 1) / 2;
 #pragma unroll 1
     for (int pk = 0; pk < npk; ++pk) {
-        const int ia = 2 * pk, ib = 2 * pk + 1;
-        const bool hasb = ib < src.n;
+        const int ia = 2 * pk, ib = src.rowpair ? 0 : 2 * pk + 1;
+        const bool hasb = src.rowpair || ib < src.n;
         // the thread index through an opaque zero: addresses are formed per
         // packed pair instead of held in registers across the loop
         const int lt = lt0 + opaque_zero();
         cx<T> v[kElemsPerThread];
         if (act) {
-            const Tin* pa = (src.img[ia] ? img1 : img0) + (size_t)row * n1;
-            const Tin* pb = (hasb && src.img[ib] ? img1 : img0) + (size_t)row * n1;
+            const Tin* pa = (src.img[ia] ? img1 : img0) + (size_t)xa * n1;
+            const Tin* pb = (hasb && src.img[ib] ? img1 : img0) + (size_t)xb * n1;
             const int ea = src.pow[ia], eb = hasb ? src.pow[ib] : 0;
             const double qa = src.ped[ia] >= 0 ? ped[src.ped[ia]] : 0.0;
             const double qb = hasb && src.ped[ib] >= 0 ? ped[src.ped[ib]] : 0.0;
@@ -74,8 +77,8 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
         for (int e = 0; e < kElemsPerThread; ++e) buf[lpad(lt + e * lp.tl)] = v[e];
         __syncthreads();
         if (act) {
-            cx<T>* za = Z + ((size_t)src.out[ia] * g.n0 + row) * g.hp;
-            cx<T>* zb = Z + ((size_t)(hasb ? src.out[ib] : 0) * g.n0 + row) * g.hp;
+            cx<T>* za = Z + ((size_t)src.out[ia] * g.n0 + xa) * g.hp;
+            cx<T>* zb = Z + ((size_t)(hasb ? src.out[ib] : 0) * g.n0 + xb) * g.hp;
 #pragma unroll 2
             for (int m = lt; m < g.h; m += lp.tl) {
                 const cx<T> a = buf[lpad(m)], b = buf[lpad(m == 0 ? 0 : n1 - m)];
@@ -272,10 +275,12 @@ hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& sr
                          IoRef<const Tin> img0, IoRef<const Tin> img1, const double* ped, cx<T>* Z,
                          const cx<T>* twt, hipStream_t st) {
     if (src.n < 1 || src.n > kMaxSrc) return hipErrorInvalidValue;
+    if (src.rowpair && (src.n != 1 || g.n0 % 2)) return hipErrorInvalidValue;
     for (int s = 0; s < src.n; ++s)
         if (src.pow[s] < 0 || src.pow[s] > kMaxDegree) return hipErrorInvalidValue;
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
-    dim3 grid((g.n0 + lp.lpw - 1) / lp.lpw);
+    const int nlines = src.rowpair ? g.n0 / 2 : g.n0;
+    dim3 grid((nlines + lp.lpw - 1) / lp.lpw);
     return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
         auto k = rowfwd_kernel<T, Tin, decltype(pl)>;
         hipError_t e = set_lds(k, lds);

@@ -14,6 +14,7 @@ struct RowSources {
     int img[kMaxSrc];         // 0 -> first image pointer, 1 -> second
     int out[kMaxSrc];         // output array index in Z
     int ped[kMaxSrc];         // index into the pedestal vector subtracted on load, -1: none
+    int rowpair;              // 1: one source (n = 1), rows 2r and 2r+1 packed in line r
 };
 
 // Column-transform jobs: input array a of Z produces spectra for x-weight
