@@ -210,25 +210,17 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
     const int line = threadIdx.x / tl, j = threadIdx.x - line * tl;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
     const int nwl = tl >> 6;                    // waves per line
-    // ir_only: one block per column block holds the spectrum in slot sslot
-    // and forms conj(X_k) X_sslot for every kernel term k (Theta products
-    // only); otherwise block (column block, kb) holds X_kb and forms its
-    // Omega products with k >= kb and its Theta product.
+    // One block per column block, its lag twiddles formed once. ir_only: it
+    // holds the spectrum in slot sslot and forms conj(X_k) X_sslot for every
+    // kernel term k (Theta products only); otherwise it holds X_kb for each
+    // kb in turn and forms its Omega products with k >= kb and its Theta
+    // product (P (P + 1) / 2 + P products per column).
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int nkb = ir_only ? 1 : g.P;
-    const int jx = slot / nkb;
-    const int kb = slot - jx * nkb;
-    const int cb = 8 * jx + xcd;
+    const int cb = 8 * slot + xcd;
     const int m = cb * lp.lpw + line;
     const bool act = m < g.h;
     const int n0 = g.n0;
     const int KO = 2 * g.w0, nblk = (2 * KO + 16) / 16;   // lag blocks of Omega (Theta uses fewer)
-    cx<T> a[16];
-    if (act) {
-        const cx<T>* A = X + ((size_t)(ir_only ? sslot : kb) * g.h + m) * n0 + j;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) a[q] = A[(size_t)q * tl];
-    }
     // FP32: the conjugated twiddles of the NB Omega blocks stay in registers
     // (one workgroup per CU leaves room); FP64: their table indices do.
     constexpr bool kTwReg = NB > 0 && sizeof(T) == 4;
@@ -245,108 +237,118 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
 #pragma unroll
             for (int r = 0; r < 16; ++r) twi[b][r] = lag_twiddle_index(n0, j, -KO + 16 * b, r);
     }
-    const int kbeg = ir_only ? 0 : kb, kend = ir_only ? g.P : g.P + 1;
-    for (int k0 = kbeg; k0 < kend; k0 += pchunk) {
-        const int k1 = min(kend, k0 + pchunk);
-        for (int kk = k0; kk < k1; ++kk) {
-            const bool theta = ir_only || kk == g.P;
-            const int k = ir_only ? kk : (theta ? sslot : kk);
-            const int K = theta ? g.w0 : KO;
-            cx<T> v[16];
-            if (act) {
-                const cx<T>* B = X + ((size_t)k * g.h + m) * n0 + j;
-                if (ir_only) {
+    const int nkb = ir_only ? 1 : g.P;
+#pragma unroll 1
+    for (int kb = 0; kb < nkb; ++kb) {
+        cx<T> a[16];
+        if (act) {
+            const cx<T>* A = X + ((size_t)(ir_only ? sslot : kb) * g.h + m) * n0 + j;
 #pragma unroll
-                    for (int q = 0; q < 16; ++q) v[q] = cmulc(B[(size_t)q * tl], a[q]);
+            for (int q = 0; q < 16; ++q) a[q] = A[(size_t)q * tl];
+        }
+        const int kbeg = ir_only ? 0 : kb, kend = ir_only ? g.P : g.P + 1;
+        for (int k0 = kbeg; k0 < kend; k0 += pchunk) {
+            const int k1 = min(kend, k0 + pchunk);
+            for (int kk = k0; kk < k1; ++kk) {
+                const bool theta = ir_only || kk == g.P;
+                const int k = ir_only ? kk : (theta ? sslot : kk);
+                const int K = theta ? g.w0 : KO;
+                cx<T> v[16];
+                if (act) {
+                    const cx<T>* B = X + ((size_t)k * g.h + m) * n0 + j;
+                    if (ir_only) {
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) v[q] = cmulc(B[(size_t)q * tl], a[q]);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) v[q] = cmulc(a[q], B[(size_t)q * tl]);
+                    }
+                    Dft<16, 1, T>::run(v);
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 16; ++q) v[q] = cmulc(a[q], B[(size_t)q * tl]);
+                    for (int q = 0; q < 16; ++q) v[q] = mk(T(0), T(0));
                 }
-                Dft<16, 1, T>::run(v);
-            } else {
+                if constexpr (kTwReg) {
+                    // Omega blocks use their own twiddles; Theta's slots select
+                    // the Omega block their lag lies in
+                    auto blocks = [&](auto theta_c) {
+                        constexpr bool TH = decltype(theta_c)::value;
 #pragma unroll
-                for (int q = 0; q < 16; ++q) v[q] = mk(T(0), T(0));
-            }
-            if constexpr (kTwReg) {
-                // Omega blocks use their own twiddles; Theta's slots select
-                // the Omega block their lag lies in
-                auto blocks = [&](auto theta_c) {
-                    constexpr bool TH = decltype(theta_c)::value;
+                        for (int blk = 0; blk < NB; ++blk) {
+                            if (16 * blk > 2 * K) break;
+                            cx<T> s[16];
 #pragma unroll
-                    for (int blk = 0; blk < NB; ++blk) {
-                        if (16 * blk > 2 * K) break;
-                        cx<T> s[16];
+                            for (int r = 0; r < 16; ++r) {
+                                cx<T> w = twv[blk][r];
+                                if constexpr (TH) {
+                                    const int tb = -K + 16 * blk, mres = tb & 15;
+                                    const int t = tb - mres + r + (r < mres ? 16 : 0);
+                                    const int ob = (t + KO) >> 4;
+                                    w = twv[0][r];
+#pragma unroll
+                                    for (int b = 1; b < NB; ++b)
+                                        if (b == ob) w = twv[b][r];
+                                }
+                                s[r] = cmul(v[r], w);
+                            }
+                            wave_transpose_sum16(s, lane);
+                            if ((lane & 3) == 0)
+                                red[(((size_t)(kk - k0) * nblk + blk) * nwv + wv) * 16 + ((lane >> 2) & 15)] = s[0];
+                        }
+                    };
+                    if (theta)
+                        blocks(std::true_type{});
+                    else
+                        blocks(std::false_type{});
+                    continue;
+                }
+                for (int blk = 0; 16 * blk <= 2 * K; ++blk) {
+                    const int tb = -K + 16 * blk;
+                    cx<T> s[16];
+                    if constexpr (NB > 0 && !kTwReg) {
+                        // Omega: block blk; Theta: slot r's lag t lies in Omega
+                        // block (t + KO) / 16 at the same slot
+                        const int mres = tb & 15;
 #pragma unroll
                         for (int r = 0; r < 16; ++r) {
-                            cx<T> w = twv[blk][r];
-                            if constexpr (TH) {
-                                const int tb = -K + 16 * blk, mres = tb & 15;
-                                const int t = tb - mres + r + (r < mres ? 16 : 0);
-                                const int ob = (t + KO) >> 4;
-                                w = twv[0][r];
+                            const int t = tb - mres + r + (r < mres ? 16 : 0);
+                            const int ob = theta ? (t + KO) >> 4 : blk;
+                            int idx = twi[0][r];
 #pragma unroll
-                                for (int b = 1; b < NB; ++b)
-                                    if (b == ob) w = twv[b][r];
-                            }
-                            s[r] = cmul(v[r], w);
+                            for (int b = 1; b < NB; ++b)
+                                if (b == ob) idx = twi[b][r];
+                            s[r] = cmul(v[r], cconj(tw[idx]));   // e^(+2 pi i j t / N0)
                         }
-                        wave_transpose_sum16(s, lane);
-                        if ((lane & 3) == 0)
-                            red[(((size_t)(kk - k0) * nblk + blk) * nwv + wv) * 16 + ((lane >> 2) & 15)] = s[0];
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            s[r] = cmul(v[r], cconj(tw[lag_twiddle_index(n0, j, tb, r)]));
                     }
-                };
-                if (theta)
-                    blocks(std::true_type{});
-                else
-                    blocks(std::false_type{});
-                continue;
-            }
-            for (int blk = 0; 16 * blk <= 2 * K; ++blk) {
-                const int tb = -K + 16 * blk;
-                cx<T> s[16];
-                if constexpr (NB > 0 && !kTwReg) {
-                    // Omega: block blk; Theta: slot r's lag t lies in Omega
-                    // block (t + KO) / 16 at the same slot
-                    const int mres = tb & 15;
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int t = tb - mres + r + (r < mres ? 16 : 0);
-                        const int ob = theta ? (t + KO) >> 4 : blk;
-                        int idx = twi[0][r];
-#pragma unroll
-                        for (int b = 1; b < NB; ++b)
-                            if (b == ob) idx = twi[b][r];
-                        s[r] = cmul(v[r], cconj(tw[idx]));   // e^(+2 pi i j t / N0)
-                    }
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 16; ++r)
-                        s[r] = cmul(v[r], cconj(tw[lag_twiddle_index(n0, j, tb, r)]));
+                    wave_transpose_sum16(s, lane);
+                    if ((lane & 3) == 0)
+                        red[(((size_t)(kk - k0) * nblk + blk) * nwv + wv) * 16 + ((lane >> 2) & 15)] = s[0];
                 }
-                wave_transpose_sum16(s, lane);
-                if ((lane & 3) == 0)
-                    red[(((size_t)(kk - k0) * nblk + blk) * nwv + wv) * 16 + ((lane >> 2) & 15)] = s[0];
             }
+            __syncthreads();
+            // line sums: one output (product, block, slot) per thread of the line
+            const int nout = (k1 - k0) * nblk * 16;
+            for (int o = j; o < nout; o += tl) {
+                const int r = o & 15, blk = (o >> 4) % nblk, ip = (o >> 4) / nblk;
+                const int kk = k0 + ip;
+                const bool theta = ir_only || kk == g.P;
+                const int K = theta ? g.w0 : KO;
+                const int tb = -K + 16 * blk;
+                const int t = tb + ((r - tb) & 15);
+                if (!act || 16 * blk > 2 * K || t > K) continue;
+                cx<T> tot = red[(((size_t)ip * nblk + blk) * nwv + line * nwl) * 16 + r];
+                for (int w = 1; w < nwl; ++w)
+                    tot = tot + red[(((size_t)ip * nblk + blk) * nwv + line * nwl + w) * 16 + r];
+                const int p = theta ? g.npair + (ir_only ? kk : kb)
+                                    : kb * g.P - kb * (kb - 1) / 2 + (kk - kb);
+                Cl[((size_t)p * g.D0 + t + 2 * g.w0) * g.hp + m] = tot;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        // line sums: one output (product, block, slot) per thread of the line
-        const int nout = (k1 - k0) * nblk * 16;
-        for (int o = j; o < nout; o += tl) {
-            const int r = o & 15, blk = (o >> 4) % nblk, ip = (o >> 4) / nblk;
-            const int kk = k0 + ip;
-            const bool theta = ir_only || kk == g.P;
-            const int K = theta ? g.w0 : KO;
-            const int tb = -K + 16 * blk;
-            const int t = tb + ((r - tb) & 15);
-            if (!act || 16 * blk > 2 * K || t > K) continue;
-            cx<T> tot = red[(((size_t)ip * nblk + blk) * nwv + line * nwl) * 16 + r];
-            for (int w = 1; w < nwl; ++w)
-                tot = tot + red[(((size_t)ip * nblk + blk) * nwv + line * nwl + w) * 16 + r];
-            const int p = theta ? g.npair + (ir_only ? kk : kb)
-                                : kb * g.P - kb * (kb - 1) / 2 + (kk - kb);
-            Cl[((size_t)p * g.D0 + t + 2 * g.w0) * g.hp + m] = tot;
-        }
-        __syncthreads();
     }
 }
 
@@ -441,7 +443,7 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
         const size_t per = (size_t)nblk * nwv * 16 * sizeof(cx<T>);
         const int pchunk = (int)std::max<size_t>(1, std::min<size_t>(g.P + 1, 32768 / per));
         const bool ir_only = p0 != 0;
-        dim3 grid((ncb + 7) / 8 * 8 * (ir_only ? 1 : g.P));
+        dim3 grid((ncb + 7) / 8 * 8);
         auto k = nblk == 1 ? lagcol_tail_kernel<T, 1>
                  : nblk == 2 ? lagcol_tail_kernel<T, 2> : lagcol_tail_kernel<T, 0>;
         hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), pchunk * per, st, g, lp, ir_only ? 1 : 0,
