@@ -210,20 +210,24 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
     const int line = threadIdx.x / tl, j = threadIdx.x - line * tl;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
     const int nwl = tl >> 6;                    // waves per line
-    // One block per column block, its lag twiddles formed once. ir_only: it
-    // holds the spectrum in slot sslot and forms conj(X_k) X_sslot for every
-    // kernel term k (Theta products only); otherwise it holds X_kb for each
-    // kb in turn and forms its Omega products with k >= kb and its Theta
-    // product (P (P + 1) / 2 + P products per column).
+    // ir_only: one block per column block holds the spectrum in slot sslot
+    // and forms conj(X_k) X_sslot for every kernel term k (Theta products
+    // only). Otherwise a block holds X_kb and forms its Omega products with
+    // k >= kb and its Theta product: with the twiddles in registers (FP32)
+    // one block per column block takes every kb in turn, so its twiddles are
+    // formed once for all P (P + 1) / 2 + P products; otherwise (FP64) the
+    // column's kb go to P blocks.
+    constexpr bool kTwReg = NB > 0 && sizeof(T) == 4;
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int cb = 8 * slot + xcd;
+    const int nkbb = (ir_only || kTwReg) ? 1 : g.P;   // blocks per column block
+    const int jx = slot / nkbb, kbb = slot - jx * nkbb;
+    const int cb = 8 * jx + xcd;
     const int m = cb * lp.lpw + line;
     const bool act = m < g.h;
     const int n0 = g.n0;
     const int KO = 2 * g.w0, nblk = (2 * KO + 16) / 16;   // lag blocks of Omega (Theta uses fewer)
     // FP32: the conjugated twiddles of the NB Omega blocks stay in registers
     // (one workgroup per CU leaves room); FP64: their table indices do.
-    constexpr bool kTwReg = NB > 0 && sizeof(T) == 4;
     int twi[(NB > 0 && !kTwReg) ? NB : 1][16];
     cx<T> twv[kTwReg ? NB : 1][16];
     if constexpr (kTwReg) {
@@ -237,9 +241,10 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
 #pragma unroll
             for (int r = 0; r < 16; ++r) twi[b][r] = lag_twiddle_index(n0, j, -KO + 16 * b, r);
     }
-    const int nkb = ir_only ? 1 : g.P;
+    const int kb_lo = (ir_only || kTwReg) ? 0 : kbb;
+    const int kb_hi = ir_only ? 1 : (kTwReg ? g.P : kbb + 1);
 #pragma unroll 1
-    for (int kb = 0; kb < nkb; ++kb) {
+    for (int kb = kb_lo; kb < kb_hi; ++kb) {
         cx<T> a[16];
         if (act) {
             const cx<T>* A = X + ((size_t)(ir_only ? sslot : kb) * g.h + m) * n0 + j;
@@ -443,7 +448,10 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
         const size_t per = (size_t)nblk * nwv * 16 * sizeof(cx<T>);
         const int pchunk = (int)std::max<size_t>(1, std::min<size_t>(g.P + 1, 32768 / per));
         const bool ir_only = p0 != 0;
-        dim3 grid((ncb + 7) / 8 * 8);
+        // one block per column block when the kernel keeps its twiddles in
+        // registers (FP32, one or two lag blocks), else one per (column, kb)
+        const bool per_column = ir_only || (sizeof(T) == 4 && (nblk == 1 || nblk == 2));
+        dim3 grid((ncb + 7) / 8 * 8 * (per_column ? 1 : g.P));
         auto k = nblk == 1 ? lagcol_tail_kernel<T, 1>
                  : nblk == 2 ? lagcol_tail_kernel<T, 2> : lagcol_tail_kernel<T, 0>;
         hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), pchunk * per, st, g, lp, ir_only ? 1 : 0,
