@@ -213,13 +213,14 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
     // ir_only: one block per column block holds the spectrum in slot sslot
     // and forms conj(X_k) X_sslot for every kernel term k (Theta products
     // only). Otherwise a block holds X_kb and forms its Omega products with
-    // k >= kb and its Theta product: with the twiddles in registers (FP32)
-    // one block per column block takes every kb in turn, so its twiddles are
-    // formed once for all P (P + 1) / 2 + P products; otherwise (FP64) the
-    // column's kb go to P blocks.
+    // k >= kb and its Theta product. With the twiddles in registers (FP32) a
+    // block takes kb and P - 1 - kb in turn (P + 2 products, the same for
+    // every block), so its twiddles serve twice as many products; the
+    // column's ceil(P/2) blocks are adjacent on one XCD and run together,
+    // sharing the spectra's columns through L2. FP64: one block per kb.
     constexpr bool kTwReg = NB > 0 && sizeof(T) == 4;
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int nkbb = (ir_only || kTwReg) ? 1 : g.P;   // blocks per column block
+    const int nkbb = ir_only ? 1 : (kTwReg ? (g.P + 1) / 2 : g.P);   // blocks per column block
     const int jx = slot / nkbb, kbb = slot - jx * nkbb;
     const int cb = 8 * jx + xcd;
     const int m = cb * lp.lpw + line;
@@ -241,10 +242,10 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
 #pragma unroll
             for (int r = 0; r < 16; ++r) twi[b][r] = lag_twiddle_index(n0, j, -KO + 16 * b, r);
     }
-    const int kb_lo = (ir_only || kTwReg) ? 0 : kbb;
-    const int kb_hi = ir_only ? 1 : (kTwReg ? g.P : kbb + 1);
+    const int nq = (!ir_only && kTwReg && g.P - 1 - kbb != kbb) ? 2 : 1;
 #pragma unroll 1
-    for (int kb = kb_lo; kb < kb_hi; ++kb) {
+    for (int half = 0; half < nq; ++half) {
+        const int kb = ir_only ? 0 : (half == 0 ? kbb : g.P - 1 - kbb);
         cx<T> a[16];
         if (act) {
             const cx<T>* A = X + ((size_t)(ir_only ? sslot : kb) * g.h + m) * n0 + j;
@@ -448,10 +449,12 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
         const size_t per = (size_t)nblk * nwv * 16 * sizeof(cx<T>);
         const int pchunk = (int)std::max<size_t>(1, std::min<size_t>(g.P + 1, 32768 / per));
         const bool ir_only = p0 != 0;
-        // one block per column block when the kernel keeps its twiddles in
-        // registers (FP32, one or two lag blocks), else one per (column, kb)
-        const bool per_column = ir_only || (sizeof(T) == 4 && (nblk == 1 || nblk == 2));
-        dim3 grid((ncb + 7) / 8 * 8 * (per_column ? 1 : g.P));
+        // blocks per column block: ceil(P/2) when the kernel keeps its
+        // twiddles in registers (FP32, one or two lag blocks; kb paired with
+        // P - 1 - kb), P otherwise, 1 for the Theta-only pass
+        const bool tw_reg = sizeof(T) == 4 && (nblk == 1 || nblk == 2);
+        const int per_col = ir_only ? 1 : (tw_reg ? (g.P + 1) / 2 : g.P);
+        dim3 grid((ncb + 7) / 8 * 8 * per_col);
         auto k = nblk == 1 ? lagcol_tail_kernel<T, 1>
                  : nblk == 2 ? lagcol_tail_kernel<T, 2> : lagcol_tail_kernel<T, 0>;
         hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), pchunk * per, st, g, lp, ir_only ? 1 : 0,
