@@ -114,45 +114,55 @@ __global__ void __launch_bounds__(256) sky_stamps_kernel(Geom g, const double* _
 }
 
 constexpr int kSkyThreads = 64;
-constexpr int kMaxTerms = (kMaxDegree + 1) * (kMaxDegree + 2) / 2;   // P at DK = kMaxDegree
 constexpr int kMaxHalfWidth = 16;                                      // largest w0, w1
 
 __global__ void __launch_bounds__(kSkyThreads) sky_kernel(Geom g, const double* __restrict__ kap1,
                                                           const double* __restrict__ bcoef,
                                                           const double* __restrict__ ped,
                                                           double* __restrict__ sky) {
-    // this rho's 1-D stamps, P x L1 doubles, staged once per block
-    __shared__ double kr[kMaxTerms * (2 * kMaxHalfWidth + 1)];
+    // this rho's 1-D stamps summed over the kernel terms of equal axis-1
+    // degree j, kj[j][b] (j <= DK, |b| <= w1), staged once per block
+    __shared__ double kj[(kMaxDegree + 1) * (2 * kMaxHalfWidth + 1)];
     const int x1 = blockIdx.x * kSkyThreads + threadIdx.x;
     const int rho = blockIdx.y;
-    const int n1 = g.n1, w1 = g.w1;
+    const int n1 = g.n1, w1 = g.w1, L1 = g.L1;
     const int R = max(g.dk, g.db);
     const double cR = ped ? ped[0] : 0.0, cS = ped ? ped[1] : 0.0;
     if (cR != 0.0) {
-        const double* src = kap1 + (size_t)rho * g.P * g.L1;
-        for (int t = threadIdx.x; t < g.P * g.L1; t += blockDim.x) kr[t] = src[t];
+        const double* src = kap1 + (size_t)rho * g.P * L1;
+        for (int t = threadIdx.x; t < (g.dk + 1) * L1; t += blockDim.x) {
+            const int jj = t / L1, b = t - jj * L1;
+            double s = 0.0;
+            for (int k = 0; k < g.P; ++k) {
+                int i, j;
+                term_ij(g.dk, k, i, j);
+                if (j == jj) s += src[(size_t)k * L1 + b];
+            }
+            kj[t] = s;
+        }
         __syncthreads();
     }
     if (x1 >= g.n1) return;
     double v = 0.0;
     if (cR != 0.0) {
-        for (int b = -w1; b <= w1; ++b) {
-            const double c = coord<double>(imod(x1 - b, n1), n1);
-            double pw[kMaxDegree + 1];
-            pw[0] = 1.0;
+        // sum over the taps b of (Horner over j in c1 of the source column
+        // x1 - b), four taps at a time in separate partial sums
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b0 = -w1; b0 <= w1; b0 += 4) {
 #pragma unroll
-            for (int e = 1; e <= kMaxDegree; ++e) pw[e] = pw[e - 1] * c;
-            for (int k = 0; k < g.P; ++k) {
-                int i, j;
-                term_ij(g.dk, k, i, j);
-                double pj = pw[0];
-#pragma unroll
-                for (int e = 1; e <= kMaxDegree; ++e)
-                    if (e == j) pj = pw[e];
-                v += kr[(size_t)k * g.L1 + b + w1] * pj;
+            for (int u = 0; u < 4; ++u) {
+                const int b = b0 + u;
+                if (b > w1) break;
+                int xs = x1 - b;   // |b| < N1: one wrap at most
+                xs += xs < 0 ? n1 : 0;
+                xs -= xs >= n1 ? n1 : 0;
+                const double c = coord<double>(xs, n1);
+                double p = kj[g.dk * L1 + b + w1];
+                for (int jj = g.dk - 1; jj >= 0; --jj) p = p * c + kj[jj * L1 + b + w1];
+                acc[u] += p;
             }
         }
-        v *= cR;
+        v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * cR;
     }
     const double c1 = coord<double>(x1, n1);
     const bool edge = rho > R;
@@ -397,8 +407,7 @@ hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<
 
 hipError_t launch_sky(const Geom& g, const double* kap, const double* bcoef, const double* ped,
                       double* kap1, double* sky, hipStream_t st) {
-    if (g.dk > kMaxDegree || g.db > kMaxDegree || g.w1 > kMaxHalfWidth || g.P > kMaxTerms)
-        return hipErrorInvalidValue;
+    if (g.dk > kMaxDegree || g.db > kMaxDegree || g.w1 > kMaxHalfWidth) return hipErrorInvalidValue;
     const int nrho = max(g.dk, g.db) + 1 + 2 * g.w0;
     if (ped) hipLaunchKernelGGL(sky_stamps_kernel, dim3(nrho), dim3(256), 0, st, g, kap, kap1);
     hipLaunchKernelGGL(sky_kernel, dim3((g.n1 + kSkyThreads - 1) / kSkyThreads, nrho),
