@@ -122,11 +122,18 @@ int64_t sfft_workspace_bytes(const sfft_params* p);
 int sfft_build_system(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void* s_fit,
                       double* G, double* h, void* stream);
 
-/* Solve G coef = h (Jacobi-scaled FP64 Cholesky). When precision is
- * SFFT_MIXED and r_fit, s_fit are given, one iterative-refinement step
- * follows: the gradient Phi^T (S_fit - Phi coef) of the current difference
- * image is recomputed from the images and the correction is solved with the
- * same factor. coef: N_u doubles, kernel coefficients then background. */
+/* Solution of Eq. 18: solve G coef = h (Jacobi-scaled FP64 Cholesky; the
+ * paper names no solver). When precision is SFFT_MIXED and r_fit, s_fit are
+ * given, one iterative-refinement step follows: the gradient
+ * Phi^T (S_fit - Phi coef) of the current difference image (Eq. 16-17) is
+ * recomputed from the images and the correction is solved with the same
+ * factor. coef: N_u doubles, kernel coefficients then background.
+ * G, h: as returned by sfft_build_system (G is read, not modified).
+ * With stream == NULL the call is synchronous: it waits for the device and
+ * returns SFFT_E_NOT_SPD (a non-positive pivot) or SFFT_E_NONFINITE (a
+ * non-finite entry of G) itself, clearing them from the context; on any
+ * other stream it returns at once and those errors come from sfft_sync.
+ * On either error coef is NaN. */
 int sfft_solve(sfft_ctx* ctx, const sfft_params* p, const double* G, const double* h,
                const void* r_fit, const void* s_fit, double* coef, void* stream);
 
@@ -176,11 +183,28 @@ int sfft_profile(sfft_ctx* ctx, int enable);
  * max_stages; only max_stages are written) or a negative error. */
 int sfft_profile_read(sfft_ctx* ctx, int max_stages, char* names, double* total_ms, int* counts);
 
+/* Test of the triangular solves' bounded waits (diagnostics). The solves
+ * run as a dataflow of 64-row blocks across workgroups, each block waiting
+ * -- with a bound -- for the blocks it depends on. With enable = 1, direct
+ * calls on this context make every such wait wait for a result that is never
+ * published, with a short bound: each wait gives up, every workgroup still
+ * runs to its end, the coefficients come out NaN and the next sfft_sync (or
+ * a synchronous sfft_solve) returns SFFT_E_HIP. enable = 0 restores normal
+ * solves. Plans already created keep the setting they were last used with
+ * until their next direct call. */
+int sfft_debug_solve_stall(sfft_ctx* ctx, int enable);
+
 /* ---- serving engine: continuous batching of independent pairs ---------- */
 
-/* One request: the fit pair, the apply pair, the outputs. All device
- * pointers stay owned by the caller and must stay valid until the request
- * completes. coef (N_u doubles) may be NULL. */
+/* One request: the fit pair, the apply pair, the outputs, and the caller's
+ * HIP stream. All device pointers stay owned by the caller and must stay
+ * valid (not freed, not reused) until sfft_poll or sfft_wait has returned
+ * the request's final status. coef (N_u doubles) may be NULL.
+ * Ordering: the request runs on an engine stream of its own, after the work
+ * enqueued on `stream` (NULL = the null stream) before sfft_submit was
+ * called -- the work that wrote the inputs or initialised the outputs.
+ * Nothing on `stream` waits for the request: read coef and d only after
+ * its final status has been returned. */
 typedef struct {
     sfft_params p;
     const void* r_fit;
@@ -189,6 +213,7 @@ typedef struct {
     const void* s;
     double* coef;
     void* d;
+    void* stream;
 } sfft_request;
 
 /* Configure the engine: `slots` concurrent requests (each on its own HIP

@@ -46,7 +46,8 @@ class _Params(ctypes.Structure):
 class _Request(ctypes.Structure):
     _fields_ = [("p", _Params), ("r_fit", ctypes.c_void_p), ("s_fit", ctypes.c_void_p),
                 ("r", ctypes.c_void_p), ("s", ctypes.c_void_p),
-                ("coef", ctypes.c_void_p), ("d", ctypes.c_void_p)]
+                ("coef", ctypes.c_void_p), ("d", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p)]
 
 
 @dataclass(frozen=True)
@@ -109,6 +110,7 @@ def lib():
             L.sfft_poll.argtypes = [vp, ctypes.c_uint64]
             L.sfft_wait.argtypes = [vp, ctypes.c_uint64]
             L.sfft_profile.argtypes = [vp, i32]
+            L.sfft_debug_solve_stall.argtypes = [vp, i32]
             L.sfft_profile_read.argtypes = [vp, i32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_int)]
             L.sfft_strerror.argtypes = [i32]
@@ -116,7 +118,7 @@ def lib():
             for name in ("sfft_create", "sfft_check_params", "sfft_build_system", "sfft_solve",
                          "sfft_subtract", "sfft_run", "sfft_sync", "sfft_lag_tables",
                          "sfft_fft_lines", "sfft_engine_config", "sfft_profile", "sfft_profile_read", "sfft_submit", "sfft_poll",
-                         "sfft_wait"):
+                         "sfft_wait", "sfft_debug_solve_stall"):
                 getattr(L, name).restype = i32
             _lib = L
     return _lib
@@ -197,6 +199,8 @@ class Context:
         return G, h
 
     def solve(self, p: Params, G, h, r_fit=None, s_fit=None, stream=None, sync=True):
+        """On the null stream (torch's default) the C call is itself
+        synchronous and raises NOT_SPD / NONFINITE directly."""
         n = p.num_unknowns
         coef = torch.empty(n, dtype=torch.float64, device=G.device)
         _check(lib().sfft_solve(self._h, ctypes.byref(p.c()), _ptr(G, torch.float64, n * n, "G"),
@@ -284,23 +288,34 @@ class Context:
     def engine_config(self, slots: int = 4):
         _check(lib().sfft_engine_config(self._h, slots), "sfft_engine_config")
 
-    def submit(self, p: Params, r_fit, s_fit, r, s, coef, d) -> int:
+    def debug_solve_stall(self, enable: bool = True):
+        """Make the triangular solves' bounded waits give up (diagnostics)."""
+        _check(lib().sfft_debug_solve_stall(self._h, 1 if enable else 0), "sfft_debug_solve_stall")
+
+    def submit(self, p: Params, r_fit, s_fit, r, s, coef, d, stream=None) -> int:
+        """Queue one request. It starts after the work already enqueued on
+        `stream` (torch's current stream by default); its tensors are held
+        here until poll/wait has returned its final status."""
         req = _Request(p.c(), self._img(p, r_fit, "r_fit"), self._img(p, s_fit, "s_fit"),
                        self._img(p, r, "r"), self._img(p, s, "s"),
                        _ptr(coef, torch.float64, p.num_unknowns, "coef") if coef is not None else None,
-                       self._img(p, d, "d"))
+                       self._img(p, d, "d"), _stream(stream))
         t = ctypes.c_uint64()
         _check(lib().sfft_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "sfft_submit")
+        self._keep[t.value] = (r_fit, s_fit, r, s, coef, d)
         return t.value
 
     def poll(self, ticket: int) -> int:
         rc = lib().sfft_poll(self._h, ticket)
+        if rc != PENDING:
+            self._keep.pop(ticket, None)
         if rc not in (OK, PENDING):
             raise SfftError(rc, f"request {ticket}")
         return rc
 
     def wait(self, ticket: int) -> int:
         rc = lib().sfft_wait(self._h, ticket)
+        self._keep.pop(ticket, None)
         if rc != OK:
             raise SfftError(rc, f"request {ticket}")
         return rc

@@ -247,8 +247,9 @@ int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out)
 
 void destroy_plan(sfft_ctx* ctx, std::unique_ptr<Plan>& pl) {
     if (!pl) return;
-    for (auto& gx : pl->graph)
-        if (gx) (void)hipGraphExecDestroy(gx);
+    for (auto& row : pl->graph)
+        for (auto& gx : row)
+            if (gx) (void)hipGraphExecDestroy(gx);
     if (pl->ws.base) (void)hipFree(pl->ws.base);
     ctx->used -= pl->ws.bytes;
     pl.reset();
@@ -267,6 +268,7 @@ static int direct_plan(sfft_ctx* ctx, const sfft_params* p, Plan** out) {
     }
     it->second->p.dtype = p->dtype;
     it->second->prof = &ctx->prof;
+    it->second->stall_test = ctx->stall_test;
     *out = it->second.get();
     return SFFT_OK;
 }
@@ -405,7 +407,8 @@ static hipError_t factor_solve(Plan& pl, const double* G, const double* h, doubl
     }
     if (!e) {
         StageTimer t_(pl.prof, "trsv", st);
-        e = launch_chol_solve(n, w.L, w.dinv, w.dsc, h, coef, 0, w.flag, w.tsv, w.tflag, 1, st);
+        e = launch_chol_solve(n, w.L, w.dinv, w.dsc, h, coef, 0, w.flag, w.tsv, w.tflag, 1,
+                              pl.stall_test, st);
     }
     return e;
 }
@@ -450,7 +453,7 @@ static hipError_t refine(Plan& pl, double* coef, int gen, hipStream_t st) {
                               w.thetaD, nullptr, nullptr, w.evecD, st);
     if (!e) e = launch_gather(g, w.omega, w.thetaD, w.lam, w.cmat, w.evecD, nullptr, w.rhs, 1, st);
     if (!e) e = launch_chol_solve(g.nu, w.L, w.dinv, w.dsc, w.rhs, coef, 1, w.flag, w.tsv, w.tflag,
-                                  gen, st);
+                                  gen, pl.stall_test, st);
     return e;
 }
 
@@ -564,7 +567,7 @@ int plan_run(Plan& pl, const void* rf, const void* sf, const void* r, const void
 int plan_run_graph(Plan& pl, const void* rf, const void* sf, const void* r, const void* s,
                    double* coef, void* d, hipStream_t st) {
     const bool same_pair = r == rf && s == sf;
-    hipGraphExec_t& gx = pl.graph[same_pair ? 0 : 1];
+    hipGraphExec_t& gx = pl.graph[same_pair ? 0 : 1][pl.p.dtype == SFFT_F64 ? 1 : 0];
     if (!gx) {
         Profiler* saved = pl.prof;
         pl.prof = nullptr;   // no timing events inside a graph
@@ -651,7 +654,12 @@ int sfft_solve(sfft_ctx* ctx, const sfft_params* p, const double* G, const doubl
     int rc = direct_plan(ctx, p, &pl);
     if (rc) return rc;
     rc = SFFT_DISPATCH(*pl, run_solve_t, G, h, r_fit, s_fit, coef, (hipStream_t)stream);
-    return rc;
+    if (rc || stream) return rc;
+    // synchronous mode: the device status of this solve
+    int f = 0;
+    if (plan_read_flag(*pl, nullptr, &f) != SFFT_OK) return SFFT_E_HIP;
+    if (f && hipMemset(pl->ws.flag, 0, sizeof(int)) != hipSuccess) return SFFT_E_HIP;
+    return flag_status(f);
 }
 
 int sfft_subtract(sfft_ctx* ctx, const sfft_params* p, const void* r, const void* s,
@@ -789,6 +797,13 @@ int sfft_profile_read(sfft_ctx* ctx, int max_stages, char* names, double* total_
         counts[i] = acc[order[i]].second;
     }
     return n;
+}
+
+int sfft_debug_solve_stall(sfft_ctx* ctx, int enable) {
+    if (!ctx) return SFFT_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->stall_test = enable ? 1 : 0;
+    return SFFT_OK;
 }
 
 const char* sfft_strerror(int s) {

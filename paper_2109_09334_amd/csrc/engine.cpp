@@ -34,6 +34,18 @@ Engine::~Engine() {
         if (s.st) (void)hipStreamDestroy(s.st);
     }
     for (auto& kv : idle_) destroy_plan(ctx_, kv.second);
+    for (auto ev : events_) (void)hipEventDestroy(ev);
+}
+
+hipEvent_t Engine::take_event() {
+    if (!events_.empty()) {
+        hipEvent_t e = events_.back();
+        events_.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
 }
 
 int Engine::submit(const sfft_request& req, uint64_t* ticket) {
@@ -43,8 +55,18 @@ int Engine::submit(const sfft_request& req, uint64_t* ticket) {
     const size_t bytes = workspace_bytes(&req.p);
     if (ctx_->budget && bytes > ctx_->budget) return SFFT_E_NOMEM;
     std::lock_guard<std::mutex> lk(mu_);
+    // The request runs on a slot stream of its own; it starts after the work
+    // enqueued on the caller's stream up to this call (which produced the
+    // inputs and, e.g., initialised the outputs).
+    (void)hipSetDevice(ctx_->device);
+    hipEvent_t ev = take_event();
+    if (!ev) return SFFT_E_HIP;
+    if (hipEventRecord(ev, (hipStream_t)req.stream) != hipSuccess) {
+        events_.push_back(ev);
+        return SFFT_E_HIP;
+    }
     const uint64_t t = next_++;
-    queue_.push_back(Job{t, req, bytes});
+    queue_.push_back(Job{t, req, bytes, ev});
     status_[t] = SFFT_PENDING;
     *ticket = t;
     cv_.notify_all();
@@ -129,12 +151,16 @@ void Engine::loop() {
             if (rc && wait_mem && running) break;       // memory frees as requests finish
             if (rc) {
                 status_[j.ticket] = rc;
+                events_.push_back(j.ready);
                 queue_.pop_front();
                 done_cv_.notify_all();
                 continue;
             }
             pl->p.dtype = j.req.p.dtype;
-            rc = graphs_ ? plan_run_graph(*pl, j.req.r_fit, j.req.s_fit, j.req.r, j.req.s,
+            rc = hipStreamWaitEvent(free_slot->st, j.ready, 0) == hipSuccess ? SFFT_OK : SFFT_E_HIP;
+            events_.push_back(j.ready);   // the wait holds the recorded state
+            if (!rc)
+                rc = graphs_ ? plan_run_graph(*pl, j.req.r_fit, j.req.s_fit, j.req.r, j.req.s,
                                           j.req.coef, j.req.d, free_slot->st)
                          : plan_run(*pl, j.req.r_fit, j.req.s_fit, j.req.r, j.req.s, j.req.coef,
                                     j.req.d, free_slot->st);
@@ -152,7 +178,10 @@ void Engine::loop() {
             queue_.pop_front();
         }
         if (stop_ && !running) {
-            for (auto& j : queue_) status_[j.ticket] = SFFT_E_INVAL;
+            for (auto& j : queue_) {
+                status_[j.ticket] = SFFT_E_INVAL;
+                events_.push_back(j.ready);
+            }
             queue_.clear();
             done_cv_.notify_all();
             return;

@@ -39,6 +39,7 @@ private:
         uint64_t ticket;
         sfft_request req;
         size_t bytes;
+        hipEvent_t ready;   // recorded on req.stream at submit: the inputs are written
     };
     struct Slot {
         hipStream_t st = nullptr;
@@ -49,6 +50,7 @@ private:
     };
     void loop();
     int acquire(const sfft_params& p, std::unique_ptr<Plan>& out, bool* wait_for_memory);
+    hipEvent_t take_event();   // caller holds mu_
 
     sfft_ctx* ctx_;
     std::vector<Slot> slots_;
@@ -56,6 +58,7 @@ private:
     std::deque<Job> queue_;
     std::map<uint64_t, int> status_;
     std::multimap<PlanKey, std::unique_ptr<Plan>> idle_;
+    std::vector<hipEvent_t> events_;   // free submit events
     std::mutex mu_;
     std::condition_variable cv_, done_cv_;
     bool stop_ = false;

@@ -18,6 +18,7 @@ constexpr int kFlagNotSpd = 1;
 constexpr int kFlagNonFinite = 2;
 constexpr int kFlagStall = 4;          // a bounded wait ran out (never expected)
 constexpr int kSolveSpin = 1 << 22;    // bound of every poll loop
+constexpr int kStallTestSpin = 64;     // the bound under the give-up test
 
 // A request's start: status flag and the solves' block flags cleared.
 __global__ void clear_flag_kernel(int* flag, int* tflag, int m) {
@@ -438,15 +439,16 @@ __global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__
 // the start of each request (clear_flag_kernel) and every solve of the
 // request has the next generation, so no solve clears them itself.
 // Every wait is on a workgroup of lower index (dispatched earlier), and each
-// poll is bounded: past the bound the block sets kFlagStall and goes on.
-// Waits (thread 0, bounded) until *f reaches gen, then makes the producer's
-// writes visible to the whole workgroup.
-__device__ __forceinline__ void wait_flag(const int* f, int gen, int* flag) {
+// poll is bounded: past the bound the block sets kFlagStall and goes on
+// (its result is then NaN).
+// Waits (thread 0, at most `spin` polls) until *f reaches gen, then makes
+// the producer's writes visible to the whole workgroup.
+__device__ __forceinline__ void wait_flag(const int* f, int gen, int spin, int* flag) {
     if (threadIdx.x == 0) {
         int spins = 0;
         while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
             __builtin_amdgcn_s_sleep(2);
-            if (++spins == kSolveSpin) {
+            if (++spins >= spin) {
                 atomicOr(flag, kFlagStall);
                 break;
             }
@@ -462,7 +464,7 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
                                                          const double* __restrict__ b,
                                                          double* __restrict__ coef, int accumulate,
                                                          int* flag, double* tsv, int* tflag,
-                                                         int gen) {
+                                                         int gen, int wait_gen, int spin) {
     __shared__ double vsh[NBK];
     const int T = (n + NBK - 1) / NBK;
     const bool fwd = (int)blockIdx.x < T;
@@ -487,7 +489,7 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
         const double* row = L + (size_t)(r0 + min(i, nb - 1)) * n;
 #pragma unroll
         for (int q = 0; q < 16; ++q) m[q] = (i < nb && c0 + q < n) ? row[c0 + q] : 0.0;
-        wait_flag(fwd ? fdone + C : bdone + C, gen, flag);
+        wait_flag(fwd ? fdone + C : bdone + C, wait_gen, spin, flag);
         if (threadIdx.x < NBK) {
             const int cc = C * NBK + threadIdx.x;
             vsh[threadIdx.x] = cc < n ? (fwd ? ys : zs)[cc] : 0.0;
@@ -499,7 +501,7 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
     }
     acc += __shfl_xor(acc, 1, 64);
     acc += __shfl_xor(acc, 2, 64);
-    if (!fwd) wait_flag(fdone + B, gen, flag);   // y_B
+    if (!fwd) wait_flag(fdone + B, wait_gen, spin, flag);   // y_B
     if (p == 0) {
         const double rhs = i < nb ? (fwd ? dsc[r0 + i] * b[r0 + i] : ys[r0 + i]) : 0.0;
         vsh[i] = i < nb ? rhs - acc : 0.0;
@@ -554,10 +556,14 @@ hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* fl
 
 hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const double* dsc,
                              const double* rhs, double* coef, int accumulate, int* flag,
-                             double* tsv, int* tflag, int gen, hipStream_t st) {
+                             double* tsv, int* tflag, int gen, int stall_test, hipStream_t st) {
     const int T = (n + NBK - 1) / NBK;
+    // under the give-up test every wait is for a generation no block
+    // publishes, with a short bound: each wait gives up, every block exits
+    const int wait_gen = stall_test ? 0x7fffffff : gen;
+    const int spin = stall_test ? kStallTestSpin : kSolveSpin;
     hipLaunchKernelGGL(trsv_flow_kernel, dim3(2 * T), dim3(256), 0, st, n, L, dinv, dsc, rhs, coef,
-                       accumulate, flag, tsv, tflag, gen);
+                       accumulate, flag, tsv, tflag, gen, wait_gen, spin);
     return hipGetLastError();
 }
 

@@ -96,9 +96,11 @@ hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* fl
 // of the solve waited past its bound (a broken dependency, never expected).
 // gen: this solve's generation within the request (1, 2, ...): the block
 // flags in tflag are cleared by launch_clear_flag at the request's start.
+// stall_test: every block-to-block wait waits for a generation that is never
+// published, with a short bound (tests the give-up path from the host).
 hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const double* dsc,
                              const double* rhs, double* coef, int accumulate, int* flag,
-                             double* tsv, int* tflag, int gen, hipStream_t st);
+                             double* tsv, int* tflag, int gen, int stall_test, hipStream_t st);
 // Status flag and the m solve block flags of a request cleared.
 hipError_t launch_clear_flag(int* flag, int* tflag, int m, hipStream_t st);
 // io[0..5] = the request's r_fit, s_fit, r, s, coef, d (slots kIo*).

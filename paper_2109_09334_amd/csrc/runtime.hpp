@@ -156,10 +156,13 @@ struct Plan {
     Twiddles t0, t1;
     Workspace ws;
     int device = 0;
-    // The whole path captured once per variant (apply pair = fit pair, or
-    // not) with every caller buffer read from ws.io; a request then costs
-    // one table write and one graph launch.
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int stall_test = 0;   // triangular solves' give-up test (direct calls only)
+    // The whole path captured once per variant -- apply pair = fit pair or
+    // not, image element type (SFFT_F32, SFFT_F64) -- with every caller
+    // buffer read from ws.io; a request then costs one table write and one
+    // graph launch. The workspace layout does not depend on the image type,
+    // so one workspace serves both, each through its own graph.
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 };
 
 int check_params(const sfft_params* p);
@@ -192,6 +195,7 @@ struct sfft_ctx {
     std::map<PlanKey, std::unique_ptr<Plan>> plans;       // direct-call plans
     std::map<std::pair<int, int>, Twiddles> twid;         // (n, mixed) -> tables
     int flag_host = 0;                                     // accumulated device flags
+    int stall_test = 0;                                    // sfft_debug_solve_stall
     sfft::Profiler prof;
     std::unique_ptr<Engine> engine;
 };

@@ -122,3 +122,64 @@ def test_graph_replays_match_eager(sfft, prec):
                 if want_coef:
                     assert torch.equal(c, cref), (prec, rep, k)
                 assert torch.equal(d, dref), (prec, rep, k)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_one_workspace_alternating_image_types(sfft, prec):
+    """One slot, so every request reuses the same workspace: F32, F64, F32,
+    F64 requests of one geometry must each equal the direct call bit for bit
+    (each image type replays its own captured graph)."""
+    pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
+    n0, n1, w, dk, db = 96, 128, 3, 2, 2
+    R32, S32 = _inputs(7, n0, n1, w, dk, db)
+    R64, S64 = R32.double(), S32.double()
+    refs = {}
+    with sfft.Context(0) as eager:
+        for dt, (R, S) in ((sfft.F32, (R32, S32)), (sfft.F64, (R64, S64))):
+            p = sfft.Params(n0, n1, w, w, dk, db, 0, pr, dt)
+            c, d = eager.run(p, R, S)
+            eager.sync()
+            refs[dt] = (p, R, S, c, d)
+    with sfft.Context(0) as ctx:
+        ctx.engine_config(1)
+        for dt in (sfft.F32, sfft.F64, sfft.F32, sfft.F64):
+            p, R, S, cref, dref = refs[dt]
+            c = torch.full((p.num_unknowns,), float("nan"), dtype=torch.float64, device="cuda")
+            d = torch.full((n0, n1), float("nan"), dtype=p.torch_dtype, device="cuda")
+            assert ctx.wait(ctx.submit(p, R, S, R, S, c, d)) == sfft.OK
+            torch.cuda.synchronize()
+            assert torch.equal(c, cref), (prec, dt)
+            assert torch.equal(d, dref), (prec, dt)
+
+
+def test_submit_is_ordered_after_the_callers_stream(sfft):
+    """Inputs written and outputs initialised on a side stream right before
+    submit (no host synchronisation): the request must see them."""
+    n0, n1, w, dk, db = 256, 256, 5, 2, 2
+    p = sfft.Params(n0, n1, w, w, dk, db, 0, sfft.MIXED, sfft.F32)
+    R, S = _inputs(9, n0, n1, w, dk, db)
+    with sfft.Context(0) as eager:
+        cref, dref = eager.run(p, R, S)
+        eager.sync()
+    side = torch.cuda.Stream()
+    with sfft.Context(0) as ctx:
+        ctx.engine_config(2)
+        jobs = []
+        for k in range(4):
+            with torch.cuda.stream(side):
+                # a long kernel first, so that a request that did not wait
+                # for this stream would read the inputs before they exist
+                big = torch.randn(4096, 4096, device="cuda")
+                for _ in range(4):
+                    big = big @ big * 1e-3
+                R2 = R * 1.0 + big[0, 0] * 0.0
+                S2 = S * 1.0 + big[0, 0] * 0.0
+                c = torch.full((p.num_unknowns,), float("nan"), dtype=torch.float64, device="cuda")
+                d = torch.full((n0, n1), float("nan"), dtype=torch.float32, device="cuda")
+                jobs.append((ctx.submit(p, R2, S2, R2, S2, c, d), c, d))
+            del R2, S2   # the binding holds them until the request is done
+        for t, c, d in jobs:
+            assert ctx.wait(t) == sfft.OK
+        torch.cuda.synchronize()
+        for t, c, d in jobs:
+            assert torch.equal(c, cref) and torch.equal(d, dref)
