@@ -8,8 +8,9 @@ engine; inputs are resident in HBM before the timed region. The JSON line
 reports the mixed-precision served form's pairs/s (value) and, beside it,
 the plain FP64 form, p50/p99 latency of a Poisson stream of the C5 size mix
 (2048^2 / 4096^2 / 6144^2), the C4 ragged batch, per-stage times
-(HIP events), the roofline of the dominant kernel and the FP64 CPU oracle
-timed on a bounded crop of the same workload.
+(HIP events), the roofline of the dominant kernel, the FP64 CPU oracle timed
+on the whole pair (all host cores; one thread on a crop), and the errors of
+this run's served results (both forms) against that oracle.
 
 Run: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -93,8 +94,14 @@ def stage_work(g, stage, s_cx):
         by = (nr + P + 1) * H * n0 * s_cx
         fl = (P + 1) * H * fft(n0)
     elif stage == "lagcol":
+        # the pruned inverse as the kernel computes it, per column and product:
+        # N0/16 threads, each 16 products (6 flop), one radix-16 DFT (176 flop:
+        # 4 x 8 butterflies, 48 flop of rotations) and, per kept 16-lag block,
+        # 16 twiddle products (96) and the 17 complex adds of the wave sum (34)
+        blocks = lambda k: (2 * k) // 16 + 1  # noqa: E731
+        per = lambda k: (n0 / 16) * (16 * 6 + 176 + blocks(k) * (16 * 6 + 17 * 2))  # noqa: E731
         by = (P + 1) * H * n0 * s_cx + nprod * (4 * w + 1) * H * s_cx
-        fl = nprod * H * (6.0 * n0 + fft(n0))
+        fl = H * (npair * per(2 * w) + P * per(w))
     elif stage == "lagrow":
         by = nprod * (4 * w + 1) * H * s_cx
         fl = nprod * (4 * w + 1) * H * 2.0 * (4 * w + 1)
@@ -113,6 +120,9 @@ def stage_work(g, stage, s_cx):
     elif stage == "rowinv":
         by = n0 * H * s_cx + 4 * n
         fl = (n0 / 2) * fft(n1)
+    elif stage == "decorrelate":   # read D, row spectra out, column pass in place, D (x) Q out
+        by = 4 * n + n0 * H * s_cx + 2 * n0 * H * s_cx + n0 * H * s_cx + 4 * n
+        fl = (n0 / 2) * fft(n1) * 2 + 2 * H * fft(n0)
     else:
         return None
     return by, fl
@@ -172,10 +182,19 @@ def main():
                     help="engine slots of the closed-loop served runs (4096^2 batches, C4)")
     ap.add_argument("--stream-slots", type=int, default=4,
                     help="engine slots of the C5 stream (latency under load)")
+    ap.add_argument("--max-batch", type=int, default=4,
+                    help="requests of one variant the engine runs as one launch per stage")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--stars", type=int, default=40000)
-    ap.add_argument("--stream-requests", type=int, default=200,
-                    help="requests per load point of the serving stream (plus 10 %% warm-up)")
+    ap.add_argument("--stream-requests", type=int, default=2000,
+                    help="requests timed per load point of the serving stream")
+    ap.add_argument("--stream-warmup", type=int, default=200,
+                    help="untimed requests before them at each load point")
+    ap.add_argument("--distinct", type=int, default=16,
+                    help="distinct resident input pairs the served requests cycle over")
+    ap.add_argument("--c4-reps", type=int, default=5, help="repetitions of the C4 batch (median)")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help=argparse.SUPPRESS)   # internal: the oracle on an N x N crop
     ap.add_argument("--mix-batch", type=int, default=48,
                     help="requests of the closed-loop run that sets the saturated rate of the mix")
     ap.add_argument("--no-stream", action="store_true")
@@ -200,6 +219,21 @@ def main():
     hw_queues = max(8, args.slots + args.stream_slots + 2)
     if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < hw_queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, hw_queues))
+
+    if args.cpu_sample:
+        # child of the cpu_baseline leg (no GPU): the oracle on an N x N crop
+        # of the pair with the threads OMP_NUM_THREADS allows
+        import oracle
+        r_np, s_np = load_pair(args.size, args.stars)
+        c = args.cpu_sample
+        rc = np.ascontiguousarray(r_np[:c, :c], dtype=np.float64)
+        sc = np.ascontiguousarray(s_np[:c, :c], dtype=np.float64)
+        t = time.perf_counter()
+        co = oracle.fit(rc, sc, 7, 7, 2, 2)
+        oracle.subtract(rc, sc, co, 7, 7, 2, 2)
+        print(json.dumps({"seconds": time.perf_counter() - t, "threads": oracle.num_threads(),
+                          "crop": c}), flush=True)
+        return
 
     import torch
     import paper_2109_09334_amd as sf
@@ -234,19 +268,37 @@ def main():
     S = torch.from_numpy(s_np).to(dev)
     ctx = sf.Context(0)           # direct per-stage calls
     srv = sf.Context(0)           # closed-loop served runs: --slots
-    srv.engine_config(args.slots)
+    srv.engine_config(args.slots, args.max_batch)
     strm = sf.Context(0)          # the C5 stream: --stream-slots
-    strm.engine_config(args.stream_slots)
+    strm.engine_config(args.stream_slots, args.max_batch)
     pm = sf.Params(n, n, w, w, dk, db, 0, sf.MIXED, sf.F32)
     p64 = sf.Params(n, n, w, w, dk, db, 0, sf.FP64, sf.F32)
     nu = pm.num_unknowns
+
+    def copies(r, s, count, seed):
+        """`count` distinct resident pairs: copy k is the pair circularly
+        shifted by seeded offsets (the same for R and S; copy 0 unshifted), so
+        requests read different HBM lines while every pair keeps the
+        workload's statistics."""
+        rng = np.random.default_rng(seed)
+        out = [(r, s)]
+        for _ in range(count - 1):
+            a, b = (int(v) for v in rng.integers(1, (r.shape[0], r.shape[1])))
+            out.append((torch.roll(r, (a, b), (0, 1)).contiguous(),
+                        torch.roll(s, (a, b), (0, 1)).contiguous()))
+        return out
+
+    pairs_c3 = copies(R, S, max(1, args.distinct), 31)
 
     def served(p, steps, warmup, batch):
         outs = [(torch.empty(nu, dtype=torch.float64, device=dev),
                  torch.empty((n, n), dtype=torch.float32, device=dev)) for _ in range(batch)]
 
         def one_step():
-            ts = [srv.submit(p, R, S, R, S, c, d) for (c, d) in outs]
+            ts = []
+            for k, (c, d) in enumerate(outs):
+                R_, S_ = pairs_c3[k % len(pairs_c3)]
+                ts.append(srv.submit(p, R_, S_, R_, S_, c, d))
             for t in ts:
                 srv.wait(t)
 
@@ -273,7 +325,8 @@ def main():
         t0 = time.time()
         pr = cached_pair(f"mix_{shape[0]}x{shape[1]}",
                          lambda shape=shape: datagen.star_pair(1000 + shape[0], *shape, w=7, dk=2, db=2))
-        mix_pairs[shape] = (torch.from_numpy(pr[0]).to(dev), torch.from_numpy(pr[1]).to(dev))
+        mix_pairs[shape] = copies(torch.from_numpy(pr[0]).to(dev), torch.from_numpy(pr[1]).to(dev),
+                                  4, shape[0])
         log(f"[bench] mix pair {shape} ready in {time.time() - t0:.1f}s")
 
     def mix_requests(count, seed):
@@ -302,8 +355,10 @@ def main():
         ps = [mix_params(rq, prec) for rq in rqs]
         outs = [take_out(p) for p in ps]
         t = time.perf_counter()
-        tk = [strm.submit(p, *mix_pairs[rq["shape"]], *mix_pairs[rq["shape"]], *o)
-              for p, rq, o in zip(ps, rqs, outs)]
+        tk = []
+        for k, (p, rq, o) in enumerate(zip(ps, rqs, outs)):
+            R_, S_ = mix_pairs[rq["shape"]][k % 4]
+            tk.append(strm.submit(p, R_, S_, R_, S_, *o))
         for x in tk:
             strm.wait(x)
         torch.cuda.synchronize()
@@ -326,7 +381,7 @@ def main():
                 rq = rqs[i]
                 p = mix_params(rq, prec)
                 o = take_out(p)
-                R_, S_ = mix_pairs[rq["shape"]]
+                R_, S_ = mix_pairs[rq["shape"]][i % 4]
                 tk = strm.submit(p, R_, S_, R_, S_, *o)
                 pending[tk] = (arrivals[i], i, p, o)
                 i += 1
@@ -338,8 +393,9 @@ def main():
                     give_out(p, o)
             time.sleep(5e-5)
         lat = np.array(lat) * 1e3
-        return {"rate_per_s": rate, "requests": count, "p50_ms": float(np.percentile(lat, 50)),
-                "p99_ms": float(np.percentile(lat, 99))}
+        return {"rate_per_s": rate, "requests": count, "warmup_requests": warm,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "served_per_s": (count + warm) / (time.perf_counter() - t_start)}
 
     def c4_batch():
         """C4: 64 ragged pairs (512^2 .. 2048x4096, w = 5, DK = DB = 1) served
@@ -362,10 +418,14 @@ def main():
             torch.cuda.synchronize()
 
         once()   # plans and workspaces
-        t = time.perf_counter()
-        once()
-        dt = time.perf_counter() - t
-        return {"pairs": 64, "pairs_per_s": 64 / dt, "ms": dt * 1e3,
+        times = []
+        for _ in range(max(1, args.c4_reps)):
+            t = time.perf_counter()
+            once()
+            times.append(time.perf_counter() - t)
+        dt = float(np.median(times))
+        return {"pairs": 64, "pairs_per_s": 64 / dt, "ms": dt * 1e3, "reps": len(times),
+                "ms_each": [1e3 * x for x in times],
                 "mpix_per_s": sum(p.n0 * p.n1 for p in ps) / dt / 1e6}
 
     # ---- served throughput: mixed form (headline), then FP64 form
@@ -392,7 +452,7 @@ def main():
             sat = mix_saturated(prec, args.mix_batch)
             pts = {}
             for frac in (0.5, 0.8, 0.95):
-                pts[str(frac)] = mix_stream(prec, frac * sat, args.stream_requests, args.stream_requests // 10)
+                pts[str(frac)] = mix_stream(prec, frac * sat, args.stream_requests, args.stream_warmup)
                 log(f"[bench] {name} stream at {frac:.2f} x {sat:.1f}/s: p50 {pts[str(frac)]['p50_ms']:.2f} "
                     f"ms p99 {pts[str(frac)]['p99_ms']:.2f} ms")
             stream[name] = {"saturated_pairs_per_s": sat, "loads": pts}
@@ -416,6 +476,23 @@ def main():
 
     st_m = stages(pm)
     st_64 = stages(p64) if not args.no_fp64 else None
+
+    # ---- noise decorrelation (App. C) of the served difference image
+    def decorr_ms(p, coef, d, iters=5):
+        ss = torch.tensor([10.0], dtype=torch.float64, device=dev)
+        out_ = torch.empty_like(d)
+        ctx.decorrelate(p, coef, d, 0.0, 0.0, ss, ss, out=out_)
+        ctx.sync()
+        ctx.profile(True)
+        for _ in range(iters):
+            ctx.decorrelate(p, coef, d, 0.0, 0.0, ss, ss, out=out_)
+        ctx.sync()
+        tot = ctx.profile_read()["decorrelate"]
+        ctx.profile(False)
+        return tot[0] / tot[1]
+
+    dec_ms = decorr_ms(pm, coef_m, d_m)
+    log(f"[bench] decorrelation: {dec_ms:.3f} ms")
     geo = {"n0": n, "n1": n, "w": w, "dk": dk, "db": db}
     # every stage against its own roofline (algorithmic bytes / flops per call
     # over the HIP-event time of the call); the reported roofline is that of
@@ -433,23 +510,57 @@ def main():
     # ((3 DK + 11) s n) plus the refinement pass ((DK + 4) s n), s = 4 B
     balg = float((3 * dk + 11 + dk + 4) * 4 * n * n)
 
-    # ---- CPU baseline: the FP64 oracle on a bounded crop of the same pair
-    cpu = None
+    # ---- CPU baseline: the FP64 oracle on the whole pair (all host cores),
+    # and the errors of this run's served results against it
+    cpu, vs_oracle = None, None
     if not args.no_cpu:
+        import subprocess
         import oracle
-        crop = int(os.environ.get("SFFT_BENCH_CPU_CROP", "2048"))
-        rc = np.ascontiguousarray(r_np[:crop, :crop], dtype=np.float64)
-        sc = np.ascontiguousarray(s_np[:crop, :crop], dtype=np.float64)
+        r64 = r_np.astype(np.float64)
+        s64 = s_np.astype(np.float64)
+        log("[bench] cpu oracle: whole pair")
         t = time.perf_counter()
-        co = oracle.fit(rc, sc, w, w, dk, db)
-        oracle.subtract(rc, sc, co, w, w, dk, db)
+        co = oracle.fit(r64, s64, w, w, dk, db)
+        do = oracle.subtract(r64, s64, co, w, w, dk, db)
         dt = time.perf_counter() - t
-        scale = (n * n) / (crop * crop)
-        cpu = {"value": 1.0 / (dt * scale), "unit": "pairs/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"oracle build+solve+subtract on the {crop}x{crop} crop of the pair "
-                         f"({dt:.1f} s), scaled x{scale:.0f} by pixel count"}
-        log(f"[bench] cpu oracle sample {dt:.1f}s")
+        log(f"[bench] cpu oracle: {dt:.1f} s")
+        nk = nu - (db + 1) * (db + 2) // 2
+
+        def errs(coef, d):
+            c = coef.cpu().numpy()
+            dd = d.cpu().numpy().astype(np.float64) - do
+            rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))  # noqa: E731
+            return {"coef_rel_kernel": rel(c[:nk], co[:nk]),
+                    "coef_rel_background": rel(c[nk:], co[nk:]),
+                    "d_rms": float(np.sqrt(np.mean(dd * dd)))}
+
+        vs_oracle = {"mixed": errs(coef_m, d_m)}
+        if res64 is not None:
+            vs_oracle["fp64"] = errs(coef_64, d_64)
+        vs_oracle["tolerance"] = {"coef_rel": 1e-6, "d_rms": 1e-4,
+                                  "note": "normwise per block; D RMS 1e-5 of the sky sigma 10"}
+        try:
+            model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo")
+                         if l.startswith("model name"))
+        except (OSError, StopIteration):
+            model = "unknown"
+        one = None
+        crop = 512
+        res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample", str(crop),
+                              "--size", str(n), "--stars", str(args.stars)],
+                             env=dict(os.environ, OMP_NUM_THREADS="1"), capture_output=True,
+                             text=True, timeout=600)
+        if res.returncode == 0:
+            j = json.loads(res.stdout.strip().splitlines()[-1])
+            scale = (n * n) / (crop * crop)
+            one = {"value": 1.0 / (j["seconds"] * scale), "unit": "pairs/s", "cores": j["threads"],
+                   "sample": f"oracle build+solve+subtract on the {crop}x{crop} crop "
+                             f"({j['seconds']:.1f} s), scaled x{scale:.0f} by pixel count"}
+            log(f"[bench] cpu oracle, 1 thread, {crop}^2 crop: {j['seconds']:.1f} s")
+        cpu = {"value": 1.0 / dt, "unit": "pairs/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "cpu_model": model,
+               "sample": f"the whole {n}x{n} pair: oracle build+solve+subtract ({dt:.1f} s)",
+               "one_thread": one}
 
     out = {
         "metric": "image pairs/sec at 4096², 15×15 kernel, DK=2; p99 latency under stream",
@@ -479,9 +590,14 @@ def main():
         "pipeline_roofline": {"bytes_per_pair": balg, "achieved_gbs": thr_m * balg / 1e9,
                               "frac": thr_m * balg / 1e9 / HBM_PEAK_GBS},
         "fp64_form": res64,
+        "vs_oracle": vs_oracle,
         "stages_ms": {"mixed": st_m, "fp64": st_64},
         "roofline": roof,
         "stage_roofline": stage_roof,
+        "decorrelation": {"ms": dec_ms, "roofline": roofline("decorrelate", dec_ms,
+                                                             stage_work(geo, "decorrelate", 8)),
+                          "note": "D (x) Q of the served 4096^2 difference image, single images, "
+                                  "sigma 10 each, kernel at the field centre, mixed form"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -33,7 +33,11 @@
  *    background terms (p, q) in the same order. Coefficients are the
  *    pixel-unit a-ring of Eq. 13 (a = N0 N1 a-ring).
  *  - Supported sizes: n0, n1 = 2^a 3^b, multiples of 16, 16 <= n <= 8192;
- *    2 w + 1 <= n; 0 <= DK, DB <= 4; w0, w1 <= 16.
+ *    4 w + 1 <= n; 0 <= DK, DB <= 4; w0, w1 <= 16. SFFT_MIXED takes FP32
+ *    images and DK <= 3 (SFFT_E_UNSUPPORTED otherwise): FP64 images would be
+ *    rounded to FP32 before its transforms, a perturbation its refinement
+ *    step cannot correct, and at DK = 4 its coefficients stay 2-4e-6 from
+ *    the FP64 optimum; those run in SFFT_FP64.
  *
  * Memory and streams: every image, matrix and vector argument is a device
  * pointer owned by the caller (for instance the storage of a PyTorch
@@ -150,6 +154,32 @@ int sfft_subtract(sfft_ctx* ctx, const sfft_params* p, const void* r, const void
 int sfft_run(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void* s_fit,
              const void* r, const void* s, double* coef, void* d, void* stream);
 
+/* Noise decorrelation of a difference image (App. C, Eq. C21-C24).
+ * The difference of co-adds of m_sci science images (white noise sigma_sci[j],
+ * matched by the stamps g_sci[j]) and n_ref reference images (sigma_ref[i],
+ * stamps h_ref[i]) convolved with the fitted kernel K,
+ *   D = sum_j S_j (x) G_j - [sum_i R_i (x) H_i] (x) K               (Eq. C21),
+ * has correlated noise; out = d (x) Q with the real, even kernel
+ *   Q^(p) = sqrt(den(0) / den(p)),
+ *   den(p) = sum_j sigma_sci[j]^2 |G^_j(p)|^2
+ *            + |K^(p)|^2 sum_i sigma_ref[i]^2 |H^_i(p)|^2           (Eq. C24)
+ * (unit kernel sum: flux is kept), circular on the n0 x n1 grid, which
+ * whitens the noise (Eq. C22-C23). K is the kernel field of `coef` (the
+ * solution of a fit with parameters p, N_u doubles) at the normalised
+ * position (u0, u1) in [-1, 1]^2 -- its spatial variation is ignored, as in
+ * App. C. Stamps: (2 w0 + 1) x (2 w1 + 1) doubles each, row-major with the
+ * offset (a, b) at [a + w0][b + w1], placed circularly on the grid;
+ * g_sci == NULL (h_ref == NULL) means unit stamps (single images, G = H = delta).
+ * 1 <= m_sci, n_ref <= 8. coef, sigma_*, g_sci, h_ref: device arrays of
+ * doubles. d, out: n0*n1 elements of p->dtype (out may equal d). The
+ * transforms run in the compute type of p->precision (FP32 in SFFT_MIXED,
+ * Q^ evaluated in it too; FP64 in SFFT_FP64). Stream-ordered; the first call
+ * for a parameter set allocates its stamp buffers (< 40 MB). */
+int sfft_decorrelate(sfft_ctx* ctx, const sfft_params* p, const double* coef, double u0, double u1,
+                     int m_sci, const double* sigma_sci, const double* g_sci, int n_ref,
+                     const double* sigma_ref, const double* h_ref, const void* d, void* out,
+                     void* stream);
+
 /* Wait for `stream` and report device-side errors recorded since the last
  * sfft_sync on this context (SFFT_E_NOT_SPD, SFFT_E_NONFINITE) or SFFT_OK. */
 int sfft_sync(sfft_ctx* ctx, void* stream);
@@ -216,14 +246,19 @@ typedef struct {
     void* stream;
 } sfft_request;
 
-/* Configure the engine: `slots` concurrent requests (each on its own HIP
- * stream with its own workspace), admission against the context's HBM
- * budget. Called once before the first submit; 0 slots = default (4).
- * Slots overlap on the device only if their streams sit on distinct hardware
- * queues: HIP gives a process GPU_MAX_HW_QUEUES of them (4 unless set in the
- * environment before HIP initialises), shared round robin by all streams,
- * so a process serving `slots` requests wants at least slots + 1. */
-int sfft_engine_config(sfft_ctx* ctx, int slots);
+/* Configure the engine: `slots` concurrent batches (each on its own HIP
+ * stream with its own workspace), each of up to `max_batch` requests
+ * (<= 16) of one variant -- the same parameters and image type, and the
+ * apply pair equal to the fit pair or not in all of them -- run as one launch
+ * per stage of the hot path (continuous batching: the head of the queue
+ * takes the later queued requests of its variant with it). Admission is
+ * against the context's HBM budget. Called once before the first submit;
+ * 0 slots = 4, max_batch 0 = 4. Slots overlap on the device only if their
+ * streams sit on distinct hardware queues: HIP gives a process
+ * GPU_MAX_HW_QUEUES of them (4 unless set in the environment before HIP
+ * initialises), shared round robin by all streams, so a process serving
+ * `slots` batches wants at least slots + 1. */
+int sfft_engine_config(sfft_ctx* ctx, int slots, int max_batch);
 
 /* Queue a request. Returns SFFT_OK and a ticket; SFFT_E_NOMEM if the
  * request can never fit the budget; SFFT_E_INVAL/UNSUPPORTED on bad params.

@@ -102,10 +102,12 @@ def lib():
             L.sfft_solve.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp]
             L.sfft_subtract.argtypes = [vp, pp, vp, vp, vp, vp, vp]
             L.sfft_run.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp, vp]
+            dbl = ctypes.c_double
+            L.sfft_decorrelate.argtypes = [vp, pp, vp, dbl, dbl, i32, vp, vp, i32, vp, vp, vp, vp, vp]
             L.sfft_sync.argtypes = [vp, vp]
             L.sfft_lag_tables.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp, vp, vp]
             L.sfft_fft_lines.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp]
-            L.sfft_engine_config.argtypes = [vp, i32]
+            L.sfft_engine_config.argtypes = [vp, i32, i32]
             L.sfft_submit.argtypes = [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]
             L.sfft_poll.argtypes = [vp, ctypes.c_uint64]
             L.sfft_wait.argtypes = [vp, ctypes.c_uint64]
@@ -116,7 +118,9 @@ def lib():
             L.sfft_strerror.argtypes = [i32]
             L.sfft_strerror.restype = ctypes.c_char_p
             for name in ("sfft_create", "sfft_check_params", "sfft_build_system", "sfft_solve",
-                         "sfft_subtract", "sfft_run", "sfft_sync", "sfft_lag_tables",
+                         "sfft_subtract", "sfft_run", "sfft_decorrelate",
+                         "sfft_sync",
+                         "sfft_lag_tables",
                          "sfft_fft_lines", "sfft_engine_config", "sfft_profile", "sfft_profile_read", "sfft_submit", "sfft_poll",
                          "sfft_wait", "sfft_debug_solve_stall"):
                 getattr(L, name).restype = i32
@@ -233,6 +237,24 @@ class Context:
                               self._img(p, d, "d"), _stream(stream)), "sfft_run")
         return coef, d
 
+    def decorrelate(self, p: Params, coef, d, u0: float, u1: float, sigma_sci, sigma_ref,
+                    g_sci=None, h_ref=None, out=None, stream=None):
+        """sfft_decorrelate: d (x) Q (App. C). sigma_sci, sigma_ref: FP64
+        device vectors (one entry per co-added image); g_sci, h_ref: FP64
+        device stamps [count][2 w0 + 1][2 w1 + 1] or None (unit stamps)."""
+        if out is None:
+            out = torch.empty((p.n0, p.n1), dtype=p.torch_dtype, device=d.device)
+        m, n = sigma_sci.numel(), sigma_ref.numel()
+        L = (2 * p.w0 + 1) * (2 * p.w1 + 1)
+        _check(lib().sfft_decorrelate(
+            self._h, ctypes.byref(p.c()), _ptr(coef, torch.float64, p.num_unknowns, "coef"),
+            float(u0), float(u1), m, _ptr(sigma_sci, torch.float64, None, "sigma_sci"),
+            _ptr(g_sci, torch.float64, m * L, "g_sci"), n,
+            _ptr(sigma_ref, torch.float64, None, "sigma_ref"),
+            _ptr(h_ref, torch.float64, n * L, "h_ref"), self._img(p, d, "d"),
+            self._img(p, out, "out"), _stream(stream)), "sfft_decorrelate")
+        return out
+
     def sync(self, stream=None):
         _check(lib().sfft_sync(self._h, _stream(stream)), "sfft_sync")
 
@@ -285,8 +307,8 @@ class Context:
         return out
 
     # -- serving engine -----------------------------------------------------
-    def engine_config(self, slots: int = 4):
-        _check(lib().sfft_engine_config(self._h, slots), "sfft_engine_config")
+    def engine_config(self, slots: int = 4, max_batch: int = 4):
+        _check(lib().sfft_engine_config(self._h, slots, max_batch), "sfft_engine_config")
 
     def debug_solve_stall(self, enable: bool = True):
         """Make the triangular solves' bounded waits give up (diagnostics)."""

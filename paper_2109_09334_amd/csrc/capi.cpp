@@ -23,6 +23,8 @@ namespace sfft {
 
 static int nterms(int d) { return (d + 1) * (d + 2) / 2; }
 
+constexpr int kMaxMixedDegree = 3;   // largest DK of the mixed form
+
 static bool radix23(int n, int* a2, int* a3) {
     int a = 0, b = 0;
     while (n > 1 && n % 2 == 0) { n /= 2; ++a; }
@@ -41,6 +43,13 @@ int check_params(const sfft_params* p) {
     if (p->precision != SFFT_FP64 && p->precision != SFFT_MIXED) return SFFT_E_INVAL;
     if (p->dtype != SFFT_F32 && p->dtype != SFFT_F64) return SFFT_E_INVAL;
     if (p->const_phot_ratio != 0 && p->const_phot_ratio != 1) return SFFT_E_INVAL;
+    // The mixed form transforms FP32 data. FP64 images would be rounded to
+    // FP32 before the transforms, a perturbation of the problem that the
+    // refinement step cannot see (its difference image comes from the same
+    // rounded transforms), and DK = 4 leaves the FP32 path's fixed point
+    // 2-4e-6 from the FP64 optimum: both run in the FP64 form.
+    if (p->precision == SFFT_MIXED && (p->dtype != SFFT_F32 || p->dk > kMaxMixedDegree))
+        return SFFT_E_UNSUPPORTED;
     int a, b;
     for (int n : {p->n0, p->n1}) {
         if (n % 16 || n > 8192 || !radix23(n, &a, &b)) return SFFT_E_UNSUPPORTED;
@@ -57,7 +66,7 @@ int64_t num_unknowns(const sfft_params* p) {
     return P * L - (p->const_phot_ratio ? (P - 1) : 0) + Q;
 }
 
-static Geom make_geom(const sfft_params* p) {
+Geom make_geom(const sfft_params* p) {
     Geom g{};
     g.n0 = p->n0;
     g.n1 = p->n1;
@@ -81,13 +90,15 @@ static Geom make_geom(const sfft_params* p) {
     g.nr = p->dk + 2;
     g.D0 = 4 * p->w0 + 1;
     g.D1 = 4 * p->w1 + 1;
+    g.nb = 1;
+    g.zs = 0;
     return g;
 }
 
 // Radix order: 16 first (the first pass runs on the registers as loaded),
 // then the small radices, then the remaining 16s (a radix-16 last pass ends in
 // registers in natural order).
-static LinePlan make_line_plan(int n) {
+LinePlan make_line_plan(int n) {
     LinePlan lp{};
     lp.n = n;
     int a, b;
@@ -112,7 +123,7 @@ static LinePlan make_line_plan(int n) {
 }
 
 // Entries of the pass twiddle tables of make_line_plan(n).
-static int pass_table_len(int n) {
+int pass_table_len(int n) {
     const LinePlan lp = make_line_plan(n);
     int len = 0, ns = 1;
     for (int p = 0; p < lp.npass; ++p) {
@@ -208,19 +219,25 @@ static int get_twiddles(sfft_ctx* ctx, int n, bool mixed, Twiddles* out) {
     return SFFT_OK;
 }
 
-// Allocate a plan (with its workspace) against the context budget. Caller
-// holds ctx->mu.
-int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out) {
+// Bytes between the workspaces of consecutive pairs of a batch.
+static size_t pair_stride(const sfft_params* p) { return (workspace_bytes(p) + 255) & ~size_t(255); }
+
+// Allocate a plan (with the workspaces of `cap` pairs) against the context
+// budget. Caller holds ctx->mu.
+int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out, int cap) {
     int rc = check_params(p);
     if (rc) return rc;
+    if (cap < 1 || cap > kMaxBatch) return SFFT_E_INVAL;
     auto pl = std::make_unique<Plan>();
     pl->p = *p;
     pl->g = make_geom(p);
     pl->lp0 = make_line_plan(p->n0);
     pl->lp1 = make_line_plan(p->n1);
     pl->device = ctx->device;
+    pl->cap = cap;
     const bool mixed = p->precision == SFFT_MIXED;
-    const size_t bytes = carve(pl->ws, pl->g, mixed ? 8 : 16, mixed ? 4 : 8, nullptr);
+    pl->g.zs = (long long)pair_stride(p);
+    const size_t bytes = (size_t)pl->g.zs * cap;
     if (ctx->budget && ctx->used + bytes > ctx->budget) return SFFT_E_NOMEM;
     rc = get_twiddles(ctx, p->n0, mixed, &pl->t0);
     if (!rc) rc = get_twiddles(ctx, p->n1, mixed, &pl->t1);
@@ -228,11 +245,13 @@ int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out)
     char* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess) return SFFT_E_NOMEM;
     carve(pl->ws, pl->g, mixed ? 8 : 16, mixed ? 4 : 8, base);
-    // The status flag starts clear: the allocation may hold a freed
+    // Every pair's status flag starts clear: the allocation may hold a freed
     // workspace's bytes, and the flag is read for every plan at a sync. The
     // 1-D polynomial sums depend on the geometry only: formed once here.
-    if (hipMemset(pl->ws.flag, 0, sizeof(int)) != hipSuccess ||
-        launch_polysum(pl->g, poly_degree(pl->g), pl->ws.sig0, pl->ws.sig1, pl->ws.pw, nullptr) !=
+    Geom all = pl->g;
+    all.nb = cap;
+    if (launch_clear_flag(all, pl->ws.flag, pl->ws.tflag, tflag_len(all), nullptr) != hipSuccess ||
+        launch_polysum(all, poly_degree(all), pl->ws.sig0, pl->ws.sig1, pl->ws.pw, nullptr) !=
             hipSuccess ||
         hipStreamSynchronize(nullptr) != hipSuccess) {
         (void)hipFree(base);
@@ -247,11 +266,14 @@ int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out)
 
 void destroy_plan(sfft_ctx* ctx, std::unique_ptr<Plan>& pl) {
     if (!pl) return;
-    for (auto& row : pl->graph)
-        for (auto& gx : row)
-            if (gx) (void)hipGraphExecDestroy(gx);
+    for (auto& a : pl->graph)
+        for (auto& b : a)
+            for (auto& gx : b)
+                if (gx) (void)hipGraphExecDestroy(gx);
     if (pl->ws.base) (void)hipFree(pl->ws.base);
     ctx->used -= pl->ws.bytes;
+    if (pl->dec) (void)hipFree(pl->dec);
+    ctx->used -= pl->dec_bytes;
     pl.reset();
 }
 
@@ -262,7 +284,7 @@ static int direct_plan(sfft_ctx* ctx, const sfft_params* p, Plan** out) {
     auto it = ctx->plans.find(k);
     if (it == ctx->plans.end()) {
         std::unique_ptr<Plan> pl;
-        rc = create_plan(ctx, p, pl);
+        rc = create_plan(ctx, p, pl, 1);
         if (rc) return rc;
         it = ctx->plans.emplace(k, std::move(pl)).first;
     }
@@ -402,12 +424,12 @@ static hipError_t factor_solve(Plan& pl, const double* G, const double* h, doubl
     hipError_t e;
     {
         StageTimer t_(pl.prof, "cholesky", st);
-        e = launch_jacobi(n, G, h, w.L, w.dsc, w.rhs, w.flag, st);
-        if (!e) e = launch_cholesky(n, w.L, w.dfac, w.dinv, w.flag, st);
+        e = launch_jacobi(pl.g, n, G, h, w.L, w.dsc, w.rhs, w.flag, st);
+        if (!e) e = launch_cholesky(pl.g, n, w.L, w.dfac, w.dinv, w.flag, st);
     }
     if (!e) {
         StageTimer t_(pl.prof, "trsv", st);
-        e = launch_chol_solve(n, w.L, w.dinv, w.dsc, h, coef, 0, w.flag, w.tsv, w.tflag, 1,
+        e = launch_chol_solve(pl.g, n, w.L, w.dinv, w.dsc, h, coef, 0, w.flag, w.tsv, w.tflag, 1,
                               pl.stall_test, st);
     }
     return e;
@@ -452,7 +474,7 @@ static hipError_t refine(Plan& pl, double* coef, int gen, hipStream_t st) {
     if (!e) e = launch_lagfix(g, 1, w.ped, w.piR, w.piD, w.sig0, w.sig1, w.pw, dm, nullptr,
                               w.thetaD, nullptr, nullptr, w.evecD, st);
     if (!e) e = launch_gather(g, w.omega, w.thetaD, w.lam, w.cmat, w.evecD, nullptr, w.rhs, 1, st);
-    if (!e) e = launch_chol_solve(g.nu, w.L, w.dinv, w.dsc, w.rhs, coef, 1, w.flag, w.tsv, w.tflag,
+    if (!e) e = launch_chol_solve(g, g.nu, w.L, w.dinv, w.dsc, w.rhs, coef, 1, w.flag, w.tsv, w.tflag,
                                   gen, pl.stall_test, st);
     return e;
 }
@@ -475,7 +497,7 @@ static int run_build_t(Plan& pl, const void* r, const void* s, double* G, double
 template <typename T, typename Tin>
 static int run_solve_t(Plan& pl, const double* G, const double* h, const void* r, const void* s,
                        double* coef, hipStream_t st) {
-    hipError_t e = launch_clear_flag(pl.ws.flag, pl.ws.tflag, tflag_len(pl.g), st);
+    hipError_t e = launch_clear_flag(pl.g, pl.ws.flag, pl.ws.tflag, tflag_len(pl.g), st);
     if (!e) e = factor_solve(pl, G, h, coef, st);
     if (!e && pl.p.precision == SFFT_MIXED && r && s) {
         e = poly_tables<Tin>(pl, (const Tin*)r, (const Tin*)s, st);
@@ -512,12 +534,12 @@ static hipError_t all_path(Plan& pl, IoRef<const Tin> rf, IoRef<const Tin> sf, I
                            IoRef<const Tin> s, IoRef<double> coef, IoRef<Tin> d, bool same_pair,
                            hipStream_t st) {
     Workspace& w = pl.ws;
-    hipError_t e = launch_clear_flag(w.flag, w.tflag, tflag_len(pl.g), st);
+    hipError_t e = launch_clear_flag(pl.g, w.flag, w.tflag, tflag_len(pl.g), st);
     if (!e) e = build<T, Tin>(pl, rf, sf, w.G, w.h, st);
     if (!e) e = factor_solve(pl, w.G, w.h, w.coef, st);
     for (int it = 0; !e && pl.p.precision == SFFT_MIXED && it < refine_steps(); ++it)
         e = refine<T>(pl, w.coef, 2 + it, st);
-    if (!e) e = launch_copy_f64(coef, w.coef, pl.g.nu, st);
+    if (!e) e = launch_copy_f64(pl.g, coef, w.coef, pl.g.nu, st);
     if (e) return e;
     if (same_pair) return difference<T, Tin>(pl, pl.g.dk + 1, true, w.coef, d, st);
     return subtract_path<T, Tin>(pl, r, s, w.coef, d, st);
@@ -530,16 +552,27 @@ static int run_all_t(Plan& pl, const void* rf, const void* sf, const void* r, co
                                        (const Tin*)s, coef, (Tin*)d, r == rf && s == sf, st));
 }
 
-// Capture of all_path with every caller buffer read from the plan's I/O
-// table (the kernels' arguments are fixed at capture).
+// all_path of the pl.g.nb pairs of a batch, every caller buffer read from
+// the pair's I/O table (launch arguments stay fixed for graph replays).
 template <typename T, typename Tin>
-static int capture_all_t(Plan& pl, bool same_pair, hipStream_t st, hipGraphExec_t* out) {
+static hipError_t table_path(Plan& pl, bool same_pair, hipStream_t st) {
     void* const* io = pl.ws.io;
-    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
-    if (e) return hip_status(e);
-    const hipError_t ek = all_path<T, Tin>(
+    return all_path<T, Tin>(
         pl, IoRef<const Tin>(io, kIoRfit), IoRef<const Tin>(io, kIoSfit), IoRef<const Tin>(io, kIoR),
         IoRef<const Tin>(io, kIoS), IoRef<double>(io, kIoCoef), IoRef<Tin>(io, kIoD), same_pair, st);
+}
+
+template <typename T, typename Tin>
+static int run_table_t(Plan& pl, bool same_pair, hipStream_t st) {
+    return hip_status(table_path<T, Tin>(pl, same_pair, st));
+}
+
+// Capture of table_path.
+template <typename T, typename Tin>
+static int capture_all_t(Plan& pl, bool same_pair, hipStream_t st, hipGraphExec_t* out) {
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+    if (e) return hip_status(e);
+    const hipError_t ek = table_path<T, Tin>(pl, same_pair, st);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(st, &graph);
     if (ek || e) {
@@ -549,6 +582,57 @@ static int capture_all_t(Plan& pl, bool same_pair, hipStream_t st, hipGraphExec_
     e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     return hip_status(e);
+}
+
+// Noise decorrelation of d into out (App. C, Eq. C21-C24): stamps of the
+// kernel at (u0, u1) and of the co-add kernels, their row DFTs, the row
+// transform of d, the column convolution with Q, the row inverse.
+constexpr int kDecStamps = 1 + 2 * kMaxCoadd;
+
+static size_t decorr_carve(const Geom& g, size_t cxb, char* base, double** stp, double** wts,
+                           void** kr) {
+    Carver c;
+    *stp = c.take<double>(base, (size_t)kDecStamps * g.L0 * g.L1);
+    *wts = c.take<double>(base, kDecStamps + 1);
+    *kr = c.take<char>(base, cxb * (size_t)kDecStamps * g.L0 * g.hp);
+    return c.off + 256;
+}
+
+template <typename T, typename Tin>
+static hipError_t decorr_path(Plan& pl, const double* coef, double u0, double u1, int M,
+                              const double* sig_s, const double* gst, int N, const double* sig_r,
+                              const double* hst, const Tin* d, Tin* out, hipStream_t st) {
+    const Geom& g = pl.g;
+    Workspace& w = pl.ws;
+    double *stp, *wts;
+    void* kr;
+    decorr_carve(g, sizeof(cx<T>), pl.dec, &stp, &wts, &kr);
+    StageTimer t_(pl.prof, "decorrelate", st);
+    hipError_t e = launch_stamps(g, coef, w.kap, st);
+    if (!e) e = launch_decorr_stamps(g, w.kap, u0, u1, M, sig_s, gst, N, sig_r, hst, stp, wts, st);
+    Geom gs = g;
+    gs.P = 1 + M + N;   // stamp rows of the row DFTs
+    if (!e) e = launch_stamp_spectra<T>(gs, stp, pl.t1.twp, cxp<T>(kr), st);
+    RowSources src{};
+    src.n = 1;
+    src.pow[0] = 0;
+    src.img[0] = 0;
+    src.out[0] = 0;
+    src.ped[0] = -1;
+    src.rowpair = 1;   // the image's rows two to a line
+    if (!e) e = launch_rowfwd<T, Tin>(g, pl.lp1, src, d, d, nullptr, cxp<T>(w.Z), cxp<T>(pl.t1.twt), st);
+    if (!e) e = launch_colconv<T>(g, pl.lp0, cxp<T>(w.Z), cxp<T>(kr), wts, M, N, cxp<T>(pl.t0.tw),
+                                  cxp<T>(pl.t0.twt), st);
+    if (!e) e = launch_rowinv<T, Tin>(g, pl.lp1, cxp<T>(w.Z), out, nullptr, cxp<T>(pl.t1.twt), st);
+    return e;
+}
+
+template <typename T, typename Tin>
+static int run_decorr_t(Plan& pl, const double* coef, double u0, double u1, int M,
+                        const double* sig_s, const double* gst, int N, const double* sig_r,
+                        const double* hst, const void* d, void* out, hipStream_t st) {
+    return hip_status(decorr_path<T, Tin>(pl, coef, u0, u1, M, sig_s, gst, N, sig_r, hst,
+                                          (const Tin*)d, (Tin*)out, st));
 }
 
 // Dispatch on (compute type, image type).
@@ -564,29 +648,40 @@ int plan_run(Plan& pl, const void* rf, const void* sf, const void* r, const void
     return SFFT_DISPATCH(pl, run_all_t, rf, sf, r, s, coef, d, st);
 }
 
-int plan_run_graph(Plan& pl, const void* rf, const void* sf, const void* r, const void* s,
-                   double* coef, void* d, hipStream_t st) {
-    const bool same_pair = r == rf && s == sf;
-    hipGraphExec_t& gx = pl.graph[same_pair ? 0 : 1][pl.p.dtype == SFFT_F64 ? 1 : 0];
-    if (!gx) {
-        Profiler* saved = pl.prof;
-        pl.prof = nullptr;   // no timing events inside a graph
-        const int rc = SFFT_DISPATCH(pl, capture_all_t, same_pair, st, &gx);
-        pl.prof = saved;
-        if (rc) {
-            gx = nullptr;
-            return rc;
+int plan_run_batch(Plan& pl, const IoBatch& io, bool same_pair, bool graphs, hipStream_t st) {
+    const int b = io.n;
+    if (b < 1 || b > pl.cap) return SFFT_E_INVAL;
+    hipError_t e = launch_set_io(pl.ws.io, pl.g.zs, io, st);
+    if (e) return SFFT_E_HIP;
+    Profiler* saved = pl.prof;
+    pl.prof = nullptr;   // no timing events inside a batch
+    int rc = SFFT_OK;
+    pl.g.nb = b;
+    if (!graphs) {
+        rc = SFFT_DISPATCH(pl, run_table_t, same_pair, st);
+    } else {
+        hipGraphExec_t& gx = pl.graph[same_pair ? 0 : 1][pl.p.dtype == SFFT_F64 ? 1 : 0][b - 1];
+        if (!gx) {
+            rc = SFFT_DISPATCH(pl, capture_all_t, same_pair, st, &gx);
+            if (rc) gx = nullptr;
         }
+        if (!rc) rc = hip_status(hipGraphLaunch(gx, st));
     }
-    hipError_t e = launch_set_io(pl.ws.io, rf, sf, r, s, coef, d, st);
-    if (!e) e = hipGraphLaunch(gx, st);
-    return hip_status(e);
+    pl.g.nb = 1;
+    pl.prof = saved;
+    return rc;
 }
 
 int plan_read_flag(Plan& pl, hipStream_t st, int* flag) {
     if (hipStreamSynchronize(st) != hipSuccess) return SFFT_E_HIP;
     if (hipMemcpy(flag, pl.ws.flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SFFT_E_HIP;
     return SFFT_OK;
+}
+
+int read_pair_flag(const Plan& pl, int z, int* flag) {
+    const int* f = reinterpret_cast<const int*>(reinterpret_cast<const char*>(pl.ws.flag) +
+                                                (size_t)z * (size_t)pl.g.zs);
+    return hipMemcpy(flag, f, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess ? SFFT_OK : SFFT_E_HIP;
 }
 
 int flag_status(int f) {
@@ -682,6 +777,36 @@ int sfft_run(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void*
     int rc = direct_plan(ctx, p, &pl);
     if (rc) return rc;
     return plan_run(*pl, r_fit, s_fit, r, s, coef, d, (hipStream_t)stream);
+}
+
+int sfft_decorrelate(sfft_ctx* ctx, const sfft_params* p, const double* coef, double u0, double u1,
+                     int m_sci, const double* sigma_sci, const double* g_sci, int n_ref,
+                     const double* sigma_ref, const double* h_ref, const void* d, void* out,
+                     void* stream) {
+    if (!ctx || !coef || !sigma_sci || !sigma_ref || !d || !out) return SFFT_E_INVAL;
+    if (m_sci < 1 || n_ref < 1) return SFFT_E_INVAL;
+    if (m_sci > kMaxCoadd || n_ref > kMaxCoadd) return SFFT_E_UNSUPPORTED;
+    if (!std::isfinite(u0) || !std::isfinite(u1)) return SFFT_E_INVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    Plan* pl;
+    int rc = direct_plan(ctx, p, &pl);
+    if (rc) return rc;
+    if (!pl->dec) {
+        double *stp, *wts;
+        void* kr;
+        const size_t bytes =
+            decorr_carve(pl->g, p->precision == SFFT_MIXED ? 8 : 16, nullptr, &stp, &wts, &kr);
+        if (ctx->budget && ctx->used + bytes > ctx->budget) return SFFT_E_NOMEM;
+        if (hipMalloc(&pl->dec, bytes) != hipSuccess) {
+            pl->dec = nullptr;
+            return SFFT_E_NOMEM;
+        }
+        pl->dec_bytes = bytes;
+        ctx->used += bytes;
+    }
+    return SFFT_DISPATCH(*pl, run_decorr_t, coef, u0, u1, m_sci, sigma_sci, g_sci, n_ref, sigma_ref,
+                         h_ref, d, out, (hipStream_t)stream);
 }
 
 int sfft_sync(sfft_ctx* ctx, void* stream) {

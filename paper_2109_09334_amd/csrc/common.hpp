@@ -45,10 +45,23 @@ __device__ __forceinline__ int opaque_zero() {
     return z;
 }
 
+// Batched launches: one launch serves a batch of pairs of one geometry,
+// blockIdx.z selecting the pair. The pairs' workspaces are laid out zs bytes
+// apart, so a workspace buffer of pair z is the argument (pair 0's) plus
+// z * zs; outside a batch z = 0. Twiddle tables are shared and never offset.
+template <typename T>
+__device__ __forceinline__ T* zoff(T* p, long long zs) {
+    return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) +
+                                    (uintptr_t)((long long)blockIdx.z * zs))
+             : p;
+}
+
 // Address of a caller-owned buffer as a kernel sees it: the argument p, or,
 // when tab is set, entry `slot` of a device table that is written before
 // each launch (a captured graph fixes its kernel arguments, the table keeps
-// the caller's buffers free to change between replays).
+// the caller's buffers free to change between replays). In a batch each
+// pair has its own table in its workspace, and a plain pointer is a
+// workspace buffer: both are offset by z * zs.
 template <typename T>
 struct IoRef {
     T* p = nullptr;
@@ -57,7 +70,9 @@ struct IoRef {
     IoRef() = default;
     __host__ __device__ IoRef(T* ptr) : p(ptr) {}
     __host__ __device__ IoRef(void* const* t, int s) : tab(t), slot(s) {}
-    __device__ __forceinline__ T* get() const { return tab ? static_cast<T*>(tab[slot]) : p; }
+    __device__ __forceinline__ T* get(long long zs) const {
+        return tab ? static_cast<T*>(zoff(tab, zs)[slot]) : zoff(p, zs);
+    }
 };
 
 // Slots of a request's caller buffers in the I/O table.
@@ -112,6 +127,8 @@ struct Geom {
     int nprod;    // npair + P spectral products per frequency
     int nr;       // real rows fed to the row transform: DK+1 weighted R, and S
     int D0, D1;   // 4w+1: lag range of the kernel-kernel tables
+    int nb;       // pairs per launch (gridDim.z), 1 outside a batch
+    long long zs; // bytes between the workspaces of consecutive pairs
 };
 
 // Monomial index t -> exponents (i, j), i ascending then j ascending.

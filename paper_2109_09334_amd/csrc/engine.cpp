@@ -1,15 +1,17 @@
 // Serving engine (see engine.hpp) and its C ABI entry points.
 #include "engine.hpp"
 
+#include <algorithm>
 #include <chrono>
 #include <cstdlib>
 
 namespace sfft {
 
-int read_plan_flag(Plan& pl, int* flag);
-
-Engine::Engine(sfft_ctx* ctx, int slots)
-    : ctx_(ctx), slots_(slots > 0 ? slots : 4), graphs_(getenv("SFFT_ENGINE_DIRECT") == nullptr) {
+Engine::Engine(sfft_ctx* ctx, int slots, int max_batch)
+    : ctx_(ctx),
+      slots_(slots > 0 ? slots : 4),
+      max_batch_(max_batch > 0 ? (max_batch < kMaxBatch ? max_batch : kMaxBatch) : 4),
+      graphs_(getenv("SFFT_ENGINE_DIRECT") == nullptr) {
     (void)hipSetDevice(ctx_->device);
     for (auto& s : slots_) {
         (void)hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking);
@@ -92,20 +94,39 @@ int Engine::wait(uint64_t ticket) {
     return s;
 }
 
-// Workspace for geometry p: an idle one of the same geometry, else a new
-// one within the budget (evicting idle workspaces of other geometries).
-// Caller holds mu_.
-int Engine::acquire(const sfft_params& p, std::unique_ptr<Plan>& out, bool* wait_for_memory) {
+// Batch key: requests that can share one launch per stage.
+static bool same_variant(const sfft_request& a, const sfft_request& b) {
+    const bool sa = a.r == a.r_fit && a.s == a.s_fit, sb = b.r == b.r_fit && b.s == b.s_fit;
+    return key_of(&a.p) == key_of(&b.p) && a.p.dtype == b.p.dtype && sa == sb;
+}
+
+static int pow2_at_least(int n) {
+    int c = 1;
+    while (c < n) c *= 2;
+    return c;
+}
+
+// Workspace for `pairs` requests of geometry p: the idle one of that
+// geometry with the least room that holds them, else a new one (room for
+// the next power of two, at most max_batch) within the budget, evicting
+// idle workspaces of other geometries. Caller holds mu_.
+int Engine::acquire(const sfft_params& p, int pairs, std::unique_ptr<Plan>& out,
+                    bool* wait_for_memory) {
     *wait_for_memory = false;
     auto key = key_of(&p);
-    auto it = idle_.find(key);
-    if (it != idle_.end()) {
-        out = std::move(it->second);
-        idle_.erase(it);
+    auto range = idle_.equal_range(key);
+    auto best = idle_.end();
+    for (auto it = range.first; it != range.second; ++it)
+        if (it->second->cap >= pairs && (best == idle_.end() || it->second->cap < best->second->cap))
+            best = it;
+    if (best != idle_.end()) {
+        out = std::move(best->second);
+        idle_.erase(best);
         return SFFT_OK;
     }
     std::lock_guard<std::mutex> ck(ctx_->mu);
-    const size_t need = workspace_bytes(&p);
+    const int cap = std::min(pow2_at_least(pairs), max_batch_);
+    const size_t need = ((workspace_bytes(&p) + 255) & ~size_t(255)) * cap;
     while (ctx_->budget && ctx_->used + need > ctx_->budget && !idle_.empty()) {
         auto victim = idle_.begin();
         destroy_plan(ctx_, victim->second);
@@ -115,7 +136,7 @@ int Engine::acquire(const sfft_params& p, std::unique_ptr<Plan>& out, bool* wait
         *wait_for_memory = true;
         return SFFT_E_NOMEM;
     }
-    return create_plan(ctx_, &p, out);
+    return create_plan(ctx_, &p, out, cap);
 }
 
 void Engine::loop() {
@@ -123,13 +144,16 @@ void Engine::loop() {
     std::unique_lock<std::mutex> lk(mu_);
     for (;;) {
         bool running = false;
-        // completions
+        // completions: every pair of the slot's batch
         for (auto& s : slots_) {
             if (!s.busy) continue;
             if (hipEventQuery(s.ev) == hipSuccess) {
-                int f = 0;
-                int rc = read_plan_flag(*s.plan, &f);
-                status_[s.ticket] = rc ? rc : flag_status(f);
+                for (size_t z = 0; z < s.tickets.size(); ++z) {
+                    int f = 0;
+                    const int rc = read_pair_flag(*s.plan, (int)z, &f);
+                    status_[s.tickets[z]] = rc ? rc : flag_status(f);
+                }
+                s.tickets.clear();
                 auto key = key_of(&s.plan->p);
                 idle_.emplace(key, std::move(s.plan));
                 s.busy = false;
@@ -138,44 +162,62 @@ void Engine::loop() {
                 running = true;
             }
         }
-        // admissions, in arrival order
+        // admissions, in arrival order: the head of the queue and the later
+        // requests of its variant, up to max_batch
         while (!queue_.empty()) {
             Slot* free_slot = nullptr;
             for (auto& s : slots_)
                 if (!s.busy) { free_slot = &s; break; }
             if (!free_slot) break;
-            Job& j = queue_.front();
+            std::vector<size_t> pick{0};
+            for (size_t i = 1; i < queue_.size() && (int)pick.size() < max_batch_; ++i)
+                if (same_variant(queue_[i].req, queue_[0].req)) pick.push_back(i);
             std::unique_ptr<Plan> pl;
             bool wait_mem = false;
-            int rc = acquire(j.req.p, pl, &wait_mem);
+            int rc = acquire(queue_[0].req.p, (int)pick.size(), pl, &wait_mem);
+            if (rc && wait_mem && pick.size() > 1) {   // the head alone may still fit
+                pick.resize(1);
+                rc = acquire(queue_[0].req.p, 1, pl, &wait_mem);
+            }
             if (rc && wait_mem && running) break;       // memory frees as requests finish
             if (rc) {
+                Job& j = queue_.front();
                 status_[j.ticket] = rc;
                 events_.push_back(j.ready);
                 queue_.pop_front();
                 done_cv_.notify_all();
                 continue;
             }
-            pl->p.dtype = j.req.p.dtype;
-            rc = hipStreamWaitEvent(free_slot->st, j.ready, 0) == hipSuccess ? SFFT_OK : SFFT_E_HIP;
-            events_.push_back(j.ready);   // the wait holds the recorded state
-            if (!rc)
-                rc = graphs_ ? plan_run_graph(*pl, j.req.r_fit, j.req.s_fit, j.req.r, j.req.s,
-                                          j.req.coef, j.req.d, free_slot->st)
-                         : plan_run(*pl, j.req.r_fit, j.req.s_fit, j.req.r, j.req.s, j.req.coef,
-                                    j.req.d, free_slot->st);
+            if ((int)pick.size() > pl->cap) pick.resize(pl->cap);
+            const sfft_request& head = queue_[0].req;
+            pl->p.dtype = head.p.dtype;
+            const bool same_pair = head.r == head.r_fit && head.s == head.s_fit;
+            IoBatch io{};
+            io.n = (int)pick.size();
+            rc = SFFT_OK;
+            for (size_t z = 0; z < pick.size(); ++z) {
+                Job& j = queue_[pick[z]];
+                if (!rc && hipStreamWaitEvent(free_slot->st, j.ready, 0) != hipSuccess) rc = SFFT_E_HIP;
+                events_.push_back(j.ready);   // the wait holds the recorded state
+                const void* ptrs[kIoUsed] = {j.req.r_fit, j.req.s_fit, j.req.r, j.req.s, j.req.coef, j.req.d};
+                for (int k = 0; k < kIoUsed; ++k) io.p[z][k] = ptrs[k];
+            }
+            if (!rc) rc = plan_run_batch(*pl, io, same_pair, graphs_, free_slot->st);
             if (!rc && hipEventRecord(free_slot->ev, free_slot->st) != hipSuccess) rc = SFFT_E_HIP;
+            std::vector<uint64_t> tickets;
+            for (size_t z = 0; z < pick.size(); ++z) tickets.push_back(queue_[pick[z]].ticket);
+            // remove the batch from the queue (later indices first)
+            for (size_t z = pick.size(); z-- > 0;) queue_.erase(queue_.begin() + (long)pick[z]);
             if (rc) {
-                status_[j.ticket] = rc;
+                for (uint64_t t : tickets) status_[t] = rc;
                 idle_.emplace(key_of(&pl->p), std::move(pl));
                 done_cv_.notify_all();
             } else {
                 free_slot->plan = std::move(pl);
                 free_slot->busy = true;
-                free_slot->ticket = j.ticket;
+                free_slot->tickets = std::move(tickets);
                 running = true;
             }
-            queue_.pop_front();
         }
         if (stop_ && !running) {
             for (auto& j : queue_) {
@@ -196,27 +238,27 @@ void Engine::loop() {
     }
 }
 
-int read_plan_flag(Plan& pl, int* flag) {
-    if (hipMemcpy(flag, pl.ws.flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SFFT_E_HIP;
-    return SFFT_OK;
-}
-
 }  // namespace sfft
 
 using sfft::Engine;
 
 extern "C" {
 
-int sfft_engine_config(sfft_ctx* ctx, int slots) {
-    if (!ctx || slots < 0 || slots > 64) return SFFT_E_INVAL;
-    if (ctx->engine) return ctx->engine->slots() == (slots ? slots : 4) ? SFFT_OK : SFFT_E_INVAL;
-    ctx->engine = std::make_unique<Engine>(ctx, slots);
+int sfft_engine_config(sfft_ctx* ctx, int slots, int max_batch) {
+    if (!ctx || slots < 0 || slots > 64 || max_batch < 0 || max_batch > sfft::kMaxBatch)
+        return SFFT_E_INVAL;
+    if (ctx->engine)
+        return ctx->engine->slots() == (slots ? slots : 4) &&
+                       ctx->engine->max_batch() == (max_batch ? max_batch : 4)
+                   ? SFFT_OK
+                   : SFFT_E_INVAL;
+    ctx->engine = std::make_unique<Engine>(ctx, slots, max_batch);
     return SFFT_OK;
 }
 
 int sfft_submit(sfft_ctx* ctx, const sfft_request* req, uint64_t* ticket) {
     if (!ctx || !req || !ticket) return SFFT_E_INVAL;
-    if (!ctx->engine) ctx->engine = std::make_unique<Engine>(ctx, 4);
+    if (!ctx->engine) ctx->engine = std::make_unique<Engine>(ctx, 4, 4);
     return ctx->engine->submit(*req, ticket);
 }
 

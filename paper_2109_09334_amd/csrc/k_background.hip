@@ -54,7 +54,8 @@ __device__ __forceinline__ void block_sum_bg(double* v, double* red) {
 template <typename Tin, int NE>
 __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, IoRef<const Tin> imgr, int da,
                                                       int dbb, int K1, double* __restrict__ vrow) {
-    const Tin* __restrict__ img = imgr.get();
+    const Tin* __restrict__ img = imgr.get(g.zs);
+    vrow = zoff(vrow, g.zs);
     __shared__ double mom[4][kMaxMom];
     __shared__ double esum[4][2][NE][kPolyRowMaxLag + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -183,6 +184,8 @@ __global__ void __launch_bounds__(256) polyrow_kernel(Geom g, IoRef<const Tin> i
 __global__ void __launch_bounds__(256) polymom_kernel(Geom g, const double* __restrict__ vrow,
                                                        int nitem, int ne,
                                                        double* __restrict__ part) {
+    vrow = zoff(vrow, g.zs);
+    part = zoff(part, g.zs);
     const int x0a = blockIdx.x * kPolyRowChunk, x0b = min(g.n0, x0a + kPolyRowChunk);
     const double rn = 1.0 / (double)(g.n0 - 1);
     for (int item = threadIdx.x; item < nitem; item += blockDim.x) {
@@ -207,7 +210,9 @@ __global__ void __launch_bounds__(256) polymom_kernel(Geom g, const double* __re
 // mom[i] = sum over the row chunks (fixed order per lane, then a wave sum).
 __global__ void __launch_bounds__(256) momsum_kernel(int nchunk, int nval,
                                                       const double* __restrict__ part,
-                                                      double* __restrict__ mom) {
+                                                      double* __restrict__ mom, long long zs) {
+    part = zoff(part, zs);
+    mom = zoff(mom, zs);
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= nval) return;
@@ -223,6 +228,9 @@ __global__ void __launch_bounds__(256) polycorr_kernel(Geom g, const double* __r
                                                         const double* __restrict__ mom, int da,
                                                         int dbb, int K0, int K1,
                                                         double* __restrict__ pi) {
+    vrow = zoff(vrow, g.zs);
+    mom = zoff(mom, g.zs);
+    pi = zoff(pi, g.zs);
     const int n0 = g.n0;
     const int nta = (da + 1) * (da + 2) / 2, ntb = (dbb + 1) * (dbb + 2) / 2;
     const int nd0 = 2 * K0 + 1, nd1 = 2 * K1 + 1;
@@ -259,6 +267,9 @@ __global__ void __launch_bounds__(256) polysum_kernel(Geom g, int dmax, double* 
                                                        double* __restrict__ sig1,
                                                        double* __restrict__ pw) {
     __shared__ double red[4];
+    sig0 = zoff(sig0, g.zs);
+    sig1 = zoff(sig1, g.zs);
+    pw = zoff(pw, g.zs);
     const int ne = g.dk + 1;
     const int ns0 = ne * ne * g.D0, ns1 = ne * ne * g.D1;
     int b = blockIdx.x;
@@ -318,6 +329,9 @@ __global__ void pedestal_kernel(Geom g, const double* __restrict__ piR, int ntbR
                                 double* __restrict__ ped) {
     (void)ntbR;
     (void)ntbS;
+    piR = zoff(piR, g.zs);
+    piS = zoff(piS, g.zs);
+    ped = zoff(ped, g.zs);
     const double n = (double)g.n0 * (double)g.n1;
     ped[0] = short_pedestal(piR[(size_t)K0R * (2 * K1R + 1) + K1R] / n);
     ped[1] = short_pedestal(piS[(size_t)K0S * (2 * K1S + 1) + K1S] / n);
@@ -337,6 +351,17 @@ __global__ void __launch_bounds__(256) lagfix_kernel(Geom g, int mode, const dou
                                                       double* __restrict__ lam,
                                                       double* __restrict__ cmat,
                                                       double* __restrict__ evec) {
+    ped = zoff(ped, g.zs);
+    piR = zoff(piR, g.zs);
+    piS = zoff(piS, g.zs);
+    sig0 = zoff(sig0, g.zs);
+    sig1 = zoff(sig1, g.zs);
+    pw = zoff(pw, g.zs);
+    omega = zoff(omega, g.zs);
+    theta = zoff(theta, g.zs);
+    lam = zoff(lam, g.zs);
+    cmat = zoff(cmat, g.zs);
+    evec = zoff(evec, g.zs);
     const double cR = ped[0], cS = mode == 0 ? ped[1] : 0.0;
     const int ntb = (dmax + 1) * (dmax + 2) / 2;
     const int ne = g.dk + 1;
@@ -406,7 +431,7 @@ hipError_t launch_polyrow(const Geom& g, IoRef<const Tin> img, int da, int dbb, 
                           double* vrow, hipStream_t st) {
     if (K1 < 0 || K1 > kPolyRowMaxLag || K1 >= g.n1) return hipErrorInvalidValue;
     if (da < 0 || dbb < 0 || dbb > kMaxDegree || da + dbb + 1 > kMaxMom) return hipErrorInvalidValue;
-    const dim3 grid((g.n0 + 3) / 4), block(256);
+    const dim3 grid((g.n0 + 3) / 4, 1, g.nb), block(256);
     switch (da + dbb + 1) {
 #define SFFT_POLYROW(NE)                                                                        \
     case NE:                                                                                    \
@@ -435,12 +460,13 @@ hipError_t launch_polycorr(const Geom& g, const double* vrow, int da, int dbb, i
     const int nchunk = (g.n0 + kPolyRowChunk - 1) / kPolyRowChunk;
     // part holds nchunk * ne * nitem partial moments, then ne * nitem sums
     double* mom = part + (size_t)nchunk * ne * nitem;
-    hipLaunchKernelGGL(polymom_kernel, dim3(nchunk), dim3(256), 0, st, g, vrow, nitem, ne, part);
+    hipLaunchKernelGGL(polymom_kernel, dim3(nchunk, 1, g.nb), dim3(256), 0, st, g, vrow, nitem, ne,
+                       part);
     const int nval = ne * nitem;
-    hipLaunchKernelGGL(momsum_kernel, dim3((nval + 3) / 4), dim3(256), 0, st, nchunk, nval, part,
-                       mom);
+    hipLaunchKernelGGL(momsum_kernel, dim3((nval + 3) / 4, 1, g.nb), dim3(256), 0, st, nchunk, nval,
+                       part, mom, g.zs);
     const int nout = nta * ntb * (2 * K0 + 1) * (2 * K1 + 1);
-    hipLaunchKernelGGL(polycorr_kernel, dim3((nout + 255) / 256), dim3(256), 0, st, g, vrow, mom, da,
+    hipLaunchKernelGGL(polycorr_kernel, dim3((nout + 255) / 256, 1, g.nb), dim3(256), 0, st, g, vrow, mom, da,
                        dbb, K0, K1, pi);
     return hipGetLastError();
 }
@@ -449,14 +475,14 @@ hipError_t launch_polysum(const Geom& g, int dmax, double* sig0, double* sig1, d
                           hipStream_t st) {
     const int ne = g.dk + 1;
     const int nb = ne * ne * (g.D0 + g.D1) + 2 * (2 * dmax + 1);
-    hipLaunchKernelGGL(polysum_kernel, dim3(nb), dim3(256), 0, st, g, dmax, sig0, sig1, pw);
+    hipLaunchKernelGGL(polysum_kernel, dim3(nb, 1, g.nb), dim3(256), 0, st, g, dmax, sig0, sig1, pw);
     return hipGetLastError();
 }
 
 hipError_t launch_pedestal(const Geom& g, const double* piR, int dmax, const double* piS,
                            double* ped, hipStream_t st) {
     const int ntb = (dmax + 1) * (dmax + 2) / 2;
-    hipLaunchKernelGGL(pedestal_kernel, dim3(1), dim3(1), 0, st, g, piR, ntb, 2 * g.w0, 2 * g.w1,
+    hipLaunchKernelGGL(pedestal_kernel, dim3(1, 1, g.nb), dim3(1), 0, st, g, piR, ntb, 2 * g.w0, 2 * g.w1,
                        piS, ntb, g.w0, g.w1, ped);
     return hipGetLastError();
 }
@@ -465,7 +491,7 @@ hipError_t launch_lagfix(const Geom& g, int mode, const double* ped, const doubl
                          const double* piS, const double* sig0, const double* sig1,
                          const double* pw, int dmax, double* omega, double* theta, double* lam,
                          double* cmat, double* evec, hipStream_t st) {
-    hipLaunchKernelGGL(lagfix_kernel, dim3(64), dim3(256), 0, st, g, mode, ped, piR, piS, sig0, sig1,
+    hipLaunchKernelGGL(lagfix_kernel, dim3(64, 1, g.nb), dim3(256), 0, st, g, mode, ped, piR, piS, sig0, sig1,
                        pw, dmax, omega, theta, lam, cmat, evec);
     return hipGetLastError();
 }

@@ -21,7 +21,9 @@ constexpr int kSolveSpin = 1 << 22;    // bound of every poll loop
 constexpr int kStallTestSpin = 64;     // the bound under the give-up test
 
 // A request's start: status flag and the solves' block flags cleared.
-__global__ void clear_flag_kernel(int* flag, int* tflag, int m) {
+__global__ void clear_flag_kernel(int* flag, int* tflag, int m, long long zs) {
+    flag = zoff(flag, zs);
+    tflag = zoff(tflag, zs);
     if (threadIdx.x == 0) *flag = 0;
     for (int i = threadIdx.x; i < m; i += blockDim.x) tflag[i] = 0;
 }
@@ -35,7 +37,12 @@ __device__ __forceinline__ double jacobi_d(double gjj) {
 
 __global__ void __launch_bounds__(256) jacobi_kernel(int n, const double* __restrict__ G,
                                                       double* __restrict__ dsc,
-                                                      double* __restrict__ L, int* flag) {
+                                                      double* __restrict__ L, int* flag,
+                                                      long long zs) {
+    G = zoff(G, zs);
+    dsc = zoff(dsc, zs);
+    L = zoff(L, zs);
+    flag = zoff(flag, zs);
     const int i = blockIdx.x;
     const double gii = G[(size_t)i * n + i];
     const double di = jacobi_d(gii);
@@ -163,7 +170,10 @@ __device__ __forceinline__ void tile_update(int n, double* __restrict__ L, int k
 // the updates of panels 0 .. k-1.
 __global__ void __launch_bounds__(kStepThreads) chol_step_kernel(int n, double* __restrict__ L,
                                                                   int k, double* __restrict__ dfac,
-                                                                  int* flag) {
+                                                                  int* flag, long long zs) {
+    L = zoff(L, zs);
+    dfac = zoff(dfac, zs);
+    flag = zoff(flag, zs);
     constexpr int RY = kStepThreads / 16;   // row groups: thread rows ty + RY a
     constexpr int RA = NBK / RY;            // rows per thread
     __shared__ double PI[NBK][NBK + 1];
@@ -343,7 +353,11 @@ __global__ void __launch_bounds__(kStepThreads) chol_step_kernel(int n, double* 
 // buffered, one barrier per row).
 __global__ void __launch_bounds__(256) diag_finish_kernel(int n, double* __restrict__ L,
                                                            const double* __restrict__ dfac,
-                                                           double* __restrict__ dinv) {
+                                                           double* __restrict__ dinv,
+                                                           long long zs) {
+    L = zoff(L, zs);
+    dfac = zoff(dfac, zs);
+    dinv = zoff(dinv, zs);
     __shared__ double Lb[NBK][NBK + 1];
     __shared__ double wrow[2][NBK];
     const int B = blockIdx.x, kb = B * NBK, nb = min(NBK, n - kb);
@@ -403,8 +417,9 @@ __global__ void __launch_bounds__(256) diag_finish_kernel(int n, double* __restr
 
 // Upper triangle of L := L^T for the strictly lower 64 x 64 tiles (I > J),
 // so that the backward solve reads rows (coalesced) instead of columns.
-__global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__ L) {
+__global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__ L, long long zs) {
     __shared__ double t[NBK][NBK + 1];
+    L = zoff(L, zs);
     int I = 1, rem = blockIdx.x;
     while (rem >= I) {
         rem -= I;
@@ -464,8 +479,17 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
                                                          const double* __restrict__ b,
                                                          double* __restrict__ coef, int accumulate,
                                                          int* flag, double* tsv, int* tflag,
-                                                         int gen, int wait_gen, int spin) {
+                                                         int gen, int wait_gen, int spin,
+                                                         long long zstride) {
     __shared__ double vsh[NBK];
+    L = zoff(L, zstride);
+    dinv = zoff(dinv, zstride);
+    dsc = zoff(dsc, zstride);
+    b = zoff(b, zstride);
+    coef = zoff(coef, zstride);
+    flag = zoff(flag, zstride);
+    tsv = zoff(tsv, zstride);
+    tflag = zoff(tflag, zstride);
     const int T = (n + NBK - 1) / NBK;
     const bool fwd = (int)blockIdx.x < T;
     const int B = fwd ? blockIdx.x : 2 * T - 1 - blockIdx.x;
@@ -528,33 +552,36 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
         __hip_atomic_store(fwd ? fdone + B : bdone + B, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-hipError_t launch_clear_flag(int* flag, int* tflag, int m, hipStream_t st) {
-    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(64), 0, st, flag, tflag, m);
+hipError_t launch_clear_flag(const Geom& g, int* flag, int* tflag, int m, hipStream_t st) {
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1, 1, g.nb), dim3(64), 0, st, flag, tflag, m, g.zs);
     return hipGetLastError();
 }
 
-hipError_t launch_jacobi(int n, const double* G, const double* h, double* L, double* dsc,
-                         double* rhs, int* flag, hipStream_t st) {
+hipError_t launch_jacobi(const Geom& g, int n, const double* G, const double* h, double* L,
+                         double* dsc, double* rhs, int* flag, hipStream_t st) {
     (void)h;
     (void)rhs;
-    hipLaunchKernelGGL(jacobi_kernel, dim3(n), dim3(256), 0, st, n, G, dsc, L, flag);
+    hipLaunchKernelGGL(jacobi_kernel, dim3(n, 1, g.nb), dim3(256), 0, st, n, G, dsc, L, flag, g.zs);
     return hipGetLastError();
 }
 
-hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* flag, hipStream_t st) {
+hipError_t launch_cholesky(const Geom& g, int n, double* L, double* dfac, double* dinv, int* flag,
+                           hipStream_t st) {
     const int T = (n + NBK - 1) / NBK;
     for (int k = 0; k < T; ++k) {
         const int npan = T - k;
         const int ntrail = k > 0 ? (T - k - 1) * (T - k) / 2 : 0;
-        hipLaunchKernelGGL(chol_step_kernel, dim3(npan + ntrail), dim3(kStepThreads), 0, st, n, L, k, dfac,
-                           flag);
+        hipLaunchKernelGGL(chol_step_kernel, dim3(npan + ntrail, 1, g.nb), dim3(kStepThreads), 0, st,
+                           n, L, k, dfac, flag, g.zs);
     }
-    hipLaunchKernelGGL(diag_finish_kernel, dim3(T), dim3(256), 0, st, n, L, dfac, dinv);
-    if (T > 1) hipLaunchKernelGGL(mirror_kernel, dim3(T * (T - 1) / 2), dim3(256), 0, st, n, L);
+    hipLaunchKernelGGL(diag_finish_kernel, dim3(T, 1, g.nb), dim3(256), 0, st, n, L, dfac, dinv, g.zs);
+    if (T > 1)
+        hipLaunchKernelGGL(mirror_kernel, dim3(T * (T - 1) / 2, 1, g.nb), dim3(256), 0, st, n, L, g.zs);
     return hipGetLastError();
 }
 
-hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const double* dsc,
+hipError_t launch_chol_solve(const Geom& g, int n, const double* L, const double* dinv,
+                             const double* dsc,
                              const double* rhs, double* coef, int accumulate, int* flag,
                              double* tsv, int* tflag, int gen, int stall_test, hipStream_t st) {
     const int T = (n + NBK - 1) / NBK;
@@ -562,8 +589,8 @@ hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const d
     // publishes, with a short bound: each wait gives up, every block exits
     const int wait_gen = stall_test ? 0x7fffffff : gen;
     const int spin = stall_test ? kStallTestSpin : kSolveSpin;
-    hipLaunchKernelGGL(trsv_flow_kernel, dim3(2 * T), dim3(256), 0, st, n, L, dinv, dsc, rhs, coef,
-                       accumulate, flag, tsv, tflag, gen, wait_gen, spin);
+    hipLaunchKernelGGL(trsv_flow_kernel, dim3(2 * T, 1, g.nb), dim3(256), 0, st, n, L, dinv, dsc, rhs,
+                       coef, accumulate, flag, tsv, tflag, gen, wait_gen, spin, g.zs);
     return hipGetLastError();
 }
 

@@ -26,8 +26,10 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
                                                       cx<T>* __restrict__ Z,
                                                       const cx<T>* __restrict__ twt) {
     cx<T>* lds = lds_base<T>();
-    const Tin* __restrict__ img0 = img0r.get();
-    const Tin* __restrict__ img1 = img1r.get();
+    const Tin* __restrict__ img0 = img0r.get(g.zs);
+    const Tin* __restrict__ img1 = img1r.get(g.zs);
+    ped = zoff(ped, g.zs);
+    Z = zoff(Z, g.zs);
     const int line = threadIdx.x / lp.tl, lt0 = threadIdx.x - line * lp.tl;
     // the line packs two sources of one image row, or (rowpair) one source
     // on the image rows xa = 2 r and xb = 2 r + 1
@@ -96,6 +98,8 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
                                                       cx<T>* __restrict__ X,
                                                       const cx<T>* __restrict__ twt) {
     cx<T>* lds = lds_base<T>();
+    Z = zoff(Z, g.zs);
+    X = zoff(X, g.zs);
     const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
     // Block -> (column block, job): workgroups are dealt to the 8 XCDs round
     // robin, so groups of 16 adjacent column blocks are kept on one XCD, where
@@ -156,14 +160,16 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
 // D(x0, .) = (1/N1) IDFT_row[Dt(x0, .)] - sky(x0, .): two rows per packed
 // complex line (Hermitian extension of each half spectrum). sky is the FP64
 // table of sky_kernel: sum_r c0(x0)^r Y_r(x1) on rows w0 <= x0 < N0 - w0,
-// tabulated rows on the 2 w0 edge rows.
+// tabulated rows on the 2 w0 edge rows; nullptr: no smooth term.
 template <typename T, typename Tout, typename PL>
 __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
                                                       const cx<T>* __restrict__ Dt,
                                                       IoRef<Tout> dr,
                                                       const double* __restrict__ sky,
                                                       const cx<T>* __restrict__ twt) {
-    Tout* __restrict__ d = dr.get();
+    Tout* __restrict__ d = dr.get(g.zs);
+    Dt = zoff(Dt, g.zs);
+    sky = zoff(sky, g.zs);
     cx<T>* lds = lds_base<T>();
     const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
     const int pr = blockIdx.x * lp.lpw + line;
@@ -196,10 +202,12 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
         const int n0 = g.n0, w0 = g.w0, R = max(g.dk, g.db);
         const double ca = coord<double>(xa, n0), cb = coord<double>(xb, n0);
         // edge rows read their own table row; interior rows the c0 powers
-        const double* ra = (xa < w0 || xa >= n0 - w0)
+        // without a table (sky == nullptr) D is the plain row inverse
+        const int nsky = sky ? R + 1 : 0;
+        const double* ra = sky && (xa < w0 || xa >= n0 - w0)
                                ? sky + (size_t)(R + 1 + (xa < w0 ? xa : xa - n0 + 2 * w0)) * n1
                                : nullptr;
-        const double* rb = (xb < w0 || xb >= n0 - w0)
+        const double* rb = sky && (xb < w0 || xb >= n0 - w0)
                                ? sky + (size_t)(R + 1 + (xb < w0 ? xb : xb - n0 + 2 * w0)) * n1
                                : nullptr;
         // four elements at a time, the table rows of each power loaded
@@ -212,7 +220,7 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
 #pragma unroll
             for (int q = 0; q < kChunk; ++q) ba[q] = bb[q] = 0.0;
             double pa = 1.0, pb = 1.0;
-            for (int r = 0; r <= R; ++r) {
+            for (int r = 0; r < nsky; ++r) {
                 double y[kChunk];
 #pragma unroll
                 for (int q = 0; q < kChunk; ++q) y[q] = sky[(size_t)r * n1 + lt + (e0 + q) * lp.tl];
@@ -280,7 +288,7 @@ hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& sr
         if (src.pow[s] < 0 || src.pow[s] > kMaxDegree) return hipErrorInvalidValue;
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     const int nlines = src.rowpair ? g.n0 / 2 : g.n0;
-    dim3 grid((nlines + lp.lpw - 1) / lp.lpw);
+    dim3 grid((nlines + lp.lpw - 1) / lp.lpw, 1, g.nb);
     return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
         auto k = rowfwd_kernel<T, Tin, decltype(pl)>;
         hipError_t e = set_lds(k, lds);
@@ -296,7 +304,7 @@ hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs,
                          cx<T>* X, const cx<T>* twt, hipStream_t st) {
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
-    dim3 grid((ncb + 127) / 128 * 128 * jobs.narr);
+    dim3 grid((ncb + 127) / 128 * 128 * jobs.narr, 1, g.nb);
     return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
         auto k = colfwd_kernel<T, decltype(pl)>;
         hipError_t e = set_lds(k, lds);
@@ -310,7 +318,7 @@ template <typename T, typename Tout>
 hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, IoRef<Tout> d,
                          const double* sky, const cx<T>* twt, hipStream_t st) {
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
-    dim3 grid((g.n0 / 2 + lp.lpw - 1) / lp.lpw);
+    dim3 grid((g.n0 / 2 + lp.lpw - 1) / lp.lpw, 1, g.nb);
     return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
         auto k = rowinv_kernel<T, Tout, decltype(pl)>;
         hipError_t e = set_lds(k, lds);

@@ -58,6 +58,13 @@ __global__ void __launch_bounds__(256) gather_kernel(Geom g, const double* __res
                                                       const double* __restrict__ ev,
                                                       double* __restrict__ G,
                                                       double* __restrict__ h, int rhs_only) {
+    om = zoff(om, g.zs);
+    th = zoff(th, g.zs);
+    la = zoff(la, g.zs);
+    cm = zoff(cm, g.zs);
+    ev = zoff(ev, g.zs);
+    G = zoff(G, g.zs);
+    h = zoff(h, g.zs);
     const int v = blockIdx.x * 64 + (threadIdx.x & 63);
     const int u = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (u >= g.nu) return;
@@ -80,39 +87,43 @@ __global__ void __launch_bounds__(256) gather_kernel(Geom g, const double* __res
 hipError_t launch_gather(const Geom& g, const double* om, const double* th, const double* la,
                          const double* cm, const double* ev, double* G, double* h, int rhs_only,
                          hipStream_t st) {
-    dim3 grid(rhs_only ? 1 : (g.nu + 63) / 64, (g.nu + 3) / 4);
+    dim3 grid(rhs_only ? 1 : (g.nu + 63) / 64, (g.nu + 3) / 4, g.nb);
     hipLaunchKernelGGL(gather_kernel, grid, dim3(256), 0, st, g, om, th, la, cm, ev, G, h, rhs_only);
     return hipGetLastError();
 }
 
 
-__global__ void set_io_kernel(void** io, const void* rf, const void* sf, const void* r,
-                              const void* s, double* coef, void* d) {
-    io[kIoRfit] = const_cast<void*>(rf);
-    io[kIoSfit] = const_cast<void*>(sf);
-    io[kIoR] = const_cast<void*>(r);
-    io[kIoS] = const_cast<void*>(s);
-    io[kIoCoef] = coef;
-    io[kIoD] = d;
+// The I/O tables of the pairs of a batch: pair z's table lies zs bytes
+// after pair z-1's; entry (z, slot) per thread.
+__global__ void set_io_kernel(void** io, long long zs, IoBatch b) {
+    const int t = threadIdx.x;
+    if (t >= b.n * kIoUsed) return;
+    const int z = t / kIoUsed, slot = t - z * kIoUsed;
+    void** tab = reinterpret_cast<void**>(reinterpret_cast<char*>(io) + (long long)z * zs);
+    tab[slot] = const_cast<void*>(b.p[z][slot]);
 }
 
 __global__ void __launch_bounds__(256) copy_f64_kernel(IoRef<double> dstr,
-                                                       const double* __restrict__ src, int n) {
-    double* __restrict__ dst = dstr.get();
+                                                       const double* __restrict__ src, int n,
+                                                       long long zs) {
+    double* __restrict__ dst = dstr.get(zs);
+    src = zoff(src, zs);
     if (!dst) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         dst[i] = src[i];
 }
 
-hipError_t launch_set_io(void** io, const void* rf, const void* sf, const void* r, const void* s,
-                         double* coef, void* d, hipStream_t st) {
-    hipLaunchKernelGGL(set_io_kernel, dim3(1), dim3(1), 0, st, io, rf, sf, r, s, coef, d);
+hipError_t launch_set_io(void** io, long long zs, const IoBatch& b, hipStream_t st) {
+    if (b.n < 1 || b.n > kMaxBatch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(set_io_kernel, dim3(1), dim3(kMaxBatch * kIoUsed), 0, st, io, zs, b);
     return hipGetLastError();
 }
 
-hipError_t launch_copy_f64(IoRef<double> dst, const double* src, int n, hipStream_t st) {
+hipError_t launch_copy_f64(const Geom& g, IoRef<double> dst, const double* src, int n,
+                           hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(copy_f64_kernel, dim3((n + 255) / 256), dim3(256), 0, st, dst, src, n);
+    hipLaunchKernelGGL(copy_f64_kernel, dim3((n + 255) / 256, 1, g.nb), dim3(256), 0, st, dst, src,
+                       n, g.zs);
     return hipGetLastError();
 }
 

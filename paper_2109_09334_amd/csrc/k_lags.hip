@@ -42,6 +42,8 @@ __global__ void __launch_bounds__(512) lagcol_kernel(Geom g, LinePlan lp, int p0
                                                       cx<T>* __restrict__ Cl,
                                                       const cx<T>* __restrict__ twt) {
     cx<T>* lds = lds_base_l<T>();
+    X = zoff(X, g.zs);
+    Cl = zoff(Cl, g.zs);
     const int line = threadIdx.x / lp.tl, lt = threadIdx.x - line * lp.tl;
     // Block -> (column block, product): the products of one column block run
     // back to back on one XCD (workgroups are dealt to the 8 XCDs round
@@ -206,6 +208,8 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
     // red[product in chunk][lag block][wave of the workgroup][16]: wave sums
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* red = reinterpret_cast<cx<T>*>(smem_raw);
+    X = zoff(X, g.zs);
+    Cl = zoff(Cl, g.zs);
     const int tl = lp.tl;                       // M: threads per line, multiple of 64
     const int line = threadIdx.x / tl, j = threadIdx.x - line * tl;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
@@ -389,6 +393,9 @@ __global__ void __launch_bounds__(256) lagrow_kernel(Geom g, int p0, const cx<T>
                                                       double* __restrict__ omega,
                                                       double* __restrict__ theta) {
     __shared__ double red[4 * kLagChunk + kLagChunk];
+    Cl = zoff(Cl, g.zs);
+    omega = zoff(omega, g.zs);
+    theta = zoff(theta, g.zs);
     const int p = p0 + blockIdx.y;
     const int r = blockIdx.x;            // row index: d0 = r - 2 w0
     const bool om = p < g.npair;
@@ -454,7 +461,7 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
         // P - 1 - kb), P otherwise, 1 for the Theta-only pass
         const bool tw_reg = sizeof(T) == 4 && (nblk == 1 || nblk == 2);
         const int per_col = ir_only ? 1 : (tw_reg ? (g.P + 1) / 2 : g.P);
-        dim3 grid((ncb + 7) / 8 * 8 * per_col);
+        dim3 grid((ncb + 7) / 8 * 8 * per_col, 1, g.nb);
         auto k = nblk == 1 ? lagcol_tail_kernel<T, 1>
                  : nblk == 2 ? lagcol_tail_kernel<T, 2> : lagcol_tail_kernel<T, 0>;
         hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), pchunk * per, st, g, lp, ir_only ? 1 : 0,
@@ -463,7 +470,7 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
     }
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
-    dim3 grid((ncb + 7) / 8 * 8 * (p1 - p0));
+    dim3 grid((ncb + 7) / 8 * 8 * (p1 - p0), 1, g.nb);
     return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
         auto k = lagcol_kernel<T, decltype(pl)>;
         if (lds > 65536) {
@@ -481,7 +488,7 @@ template <typename T>
 hipError_t launch_lagrow(const Geom& g, int p0, int p1, const cx<T>* Cl, const double* twp,
                          double* omega, double* theta, hipStream_t st) {
     if (p1 <= p0) return hipSuccess;
-    dim3 grid(g.D0, p1 - p0);
+    dim3 grid(g.D0, p1 - p0, g.nb);
     hipLaunchKernelGGL(lagrow_kernel<T>, grid, dim3(256), 0, st, g, p0, Cl, twp, omega, theta);
     return hipGetLastError();
 }

@@ -32,6 +32,8 @@ __device__ __forceinline__ int coef_index(const Geom& g, int k, int a, int b) {
 __global__ void __launch_bounds__(256) stamps_kernel(Geom g, const double* __restrict__ coef,
                                                       double* __restrict__ kap) {
     __shared__ double red[4];
+    coef = zoff(coef, g.zs);
+    kap = zoff(kap, g.zs);
     const int k = blockIdx.x;
     const int L = g.L0 * g.L1;
     double off = 0.0;
@@ -57,6 +59,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) stamp_spectra_kernel(Geom g, const double* __restrict__ kap,
                                                              const double* __restrict__ twp,
                                                              cx<T>* __restrict__ Kt) {
+    kap = zoff(kap, g.zs);
+    Kt = zoff(Kt, g.zs);
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     const int row = blockIdx.y;   // k * L0 + a0 index
     if (m >= g.h) return;
@@ -89,6 +93,8 @@ __global__ void __launch_bounds__(256) stamp_spectra_kernel(Geom g, const double
 // sky[max(DK, DB) + 1 + e][x1].
 __global__ void __launch_bounds__(256) sky_stamps_kernel(Geom g, const double* __restrict__ kap,
                                                           double* __restrict__ kap1) {
+    kap = zoff(kap, g.zs);
+    kap1 = zoff(kap1, g.zs);
     const int rho = blockIdx.x;
     const int R = max(g.dk, g.db);
     const int L = g.L0 * g.L1;
@@ -123,6 +129,10 @@ __global__ void __launch_bounds__(kSkyThreads) sky_kernel(Geom g, const double* 
     // this rho's 1-D stamps summed over the kernel terms of equal axis-1
     // degree j, kj[j][b] (j <= DK, |b| <= w1), staged once per block
     __shared__ double kj[(kMaxDegree + 1) * (2 * kMaxHalfWidth + 1)];
+    kap1 = zoff(kap1, g.zs);
+    bcoef = zoff(bcoef, g.zs);
+    ped = zoff(ped, g.zs);
+    sky = zoff(sky, g.zs);
     const int x1 = blockIdx.x * kSkyThreads + threadIdx.x;
     const int rho = blockIdx.y;
     const int n1 = g.n1, w1 = g.w1, L1 = g.L1;
@@ -193,6 +203,9 @@ __global__ void __launch_bounds__(256) stencil_kernel(Geom g, const cx<T>* __res
                                                        const cx<T>* __restrict__ Kt,
                                                        cx<T>* __restrict__ Dt) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    Z = zoff(Z, g.zs);
+    Kt = zoff(Kt, g.zs);
+    Dt = zoff(Dt, g.zs);
     const int nsrc = kStTile + 2 * g.w0;
     cx<T>* zt = reinterpret_cast<cx<T>*>(smem_raw);            // [nsrc][kStCols]
     T* ct = reinterpret_cast<T*>(zt + (size_t)nsrc * kStCols);  // [nsrc] source coordinates
@@ -273,6 +286,9 @@ __global__ void __launch_bounds__(256) stencil_reg_kernel(Geom g, const cx<T>* _
     constexpr int L0 = 2 * W0 + 1;
     constexpr int P = (DK + 1) * (DK + 2) / 2;
     __shared__ cx<T> ktl[P * L0][64];
+    Z = zoff(Z, g.zs);
+    Kt = zoff(Kt, g.zs);
+    Dt = zoff(Dt, g.zs);
     const int mc = threadIdx.x & 63;
     const int m = blockIdx.x * 64 + mc;
     // one wave per row group: x0b, the source rows and their coordinates are
@@ -345,7 +361,7 @@ template <typename T, int DK, int W0>
 static hipError_t launch_stencil_reg(const Geom& g, const cx<T>* Z, int zs, const cx<T>* Kt,
                                      cx<T>* Dt, hipStream_t st) {
     constexpr int NO = 16;
-    dim3 grid((g.h + 63) / 64, (g.n0 + 4 * NO - 1) / (4 * NO));
+    dim3 grid((g.h + 63) / 64, (g.n0 + 4 * NO - 1) / (4 * NO), g.nb);
     hipLaunchKernelGGL((stencil_reg_kernel<T, DK, W0, NO>), grid, dim3(256), 0, st, g, Z, zs, Kt, Dt);
     return hipGetLastError();
 }
@@ -365,14 +381,14 @@ static bool stencil_reg_w(const Geom& g, const cx<T>* Z, int zs, const cx<T>* Kt
 }
 
 hipError_t launch_stamps(const Geom& g, const double* coef, double* kap, hipStream_t st) {
-    hipLaunchKernelGGL(stamps_kernel, dim3(g.P), dim3(256), 0, st, g, coef, kap);
+    hipLaunchKernelGGL(stamps_kernel, dim3(g.P, 1, g.nb), dim3(256), 0, st, g, coef, kap);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_stamp_spectra(const Geom& g, const double* kap, const double* twp, cx<T>* Kt,
                                 hipStream_t st) {
-    hipLaunchKernelGGL(stamp_spectra_kernel<T>, dim3((g.h + 255) / 256, g.P * g.L0), dim3(256), 0,
+    hipLaunchKernelGGL(stamp_spectra_kernel<T>, dim3((g.h + 255) / 256, g.P * g.L0, g.nb), dim3(256), 0,
                        st, g, kap, twp, Kt);
     return hipGetLastError();
 }
@@ -400,7 +416,7 @@ hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(stencil_kernel<T>, dim3((g.h + kStCols - 1) / kStCols, (g.n0 + kStTile - 1) / kStTile),
+    hipLaunchKernelGGL(stencil_kernel<T>, dim3((g.h + kStCols - 1) / kStCols, (g.n0 + kStTile - 1) / kStTile, g.nb),
                        dim3(256), lds, st, g, Z, zs_index, Kt, Dt);
     return hipGetLastError();
 }
@@ -409,8 +425,8 @@ hipError_t launch_sky(const Geom& g, const double* kap, const double* bcoef, con
                       double* kap1, double* sky, hipStream_t st) {
     if (g.dk > kMaxDegree || g.db > kMaxDegree || g.w1 > kMaxHalfWidth) return hipErrorInvalidValue;
     const int nrho = max(g.dk, g.db) + 1 + 2 * g.w0;
-    if (ped) hipLaunchKernelGGL(sky_stamps_kernel, dim3(nrho), dim3(256), 0, st, g, kap, kap1);
-    hipLaunchKernelGGL(sky_kernel, dim3((g.n1 + kSkyThreads - 1) / kSkyThreads, nrho),
+    if (ped) hipLaunchKernelGGL(sky_stamps_kernel, dim3(nrho, 1, g.nb), dim3(256), 0, st, g, kap, kap1);
+    hipLaunchKernelGGL(sky_kernel, dim3((g.n1 + kSkyThreads - 1) / kSkyThreads, nrho, g.nb),
                        dim3(kSkyThreads), 0, st, g, kap1, bcoef, ped, sky);
     return hipGetLastError();
 }

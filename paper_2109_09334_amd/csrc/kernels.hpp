@@ -83,13 +83,14 @@ hipError_t launch_gather(const Geom& g, const double* om, const double* th, cons
                          hipStream_t st);
 
 // Cholesky of the Jacobi-scaled normal matrix and triangular solves.
-hipError_t launch_jacobi(int n, const double* G, const double* h, double* L, double* dsc,
-                         double* rhs, int* flag, hipStream_t st);
+// (g: the batch -- nb pairs zs bytes apart -- of the launches below.)
+hipError_t launch_jacobi(const Geom& g, int n, const double* G, const double* h, double* L,
+                         double* dsc, double* rhs, int* flag, hipStream_t st);
 // dfac: scratch of ceil(n/64) * 64 * 64 doubles for the panels' diagonal
 // factors; dinv: ceil(n/64) * 2 * 64 * 64 doubles, the inverses of the
 // diagonal blocks and their transposes (read by launch_chol_solve). L ends
 // with the factor in its lower and its transpose in its upper triangle.
-hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* flag,
+hipError_t launch_cholesky(const Geom& g, int n, double* L, double* dfac, double* dinv, int* flag,
                            hipStream_t st);
 // coef (+)= solution of G c = rhs (rhs is read only). tsv: scratch of 2 n
 // doubles, tflag: of 2 ceil(n/64) ints. flag gains kFlagStall if a block
@@ -98,16 +99,25 @@ hipError_t launch_cholesky(int n, double* L, double* dfac, double* dinv, int* fl
 // flags in tflag are cleared by launch_clear_flag at the request's start.
 // stall_test: every block-to-block wait waits for a generation that is never
 // published, with a short bound (tests the give-up path from the host).
-hipError_t launch_chol_solve(int n, const double* L, const double* dinv, const double* dsc,
+hipError_t launch_chol_solve(const Geom& g, int n, const double* L, const double* dinv,
+                             const double* dsc,
                              const double* rhs, double* coef, int accumulate, int* flag,
                              double* tsv, int* tflag, int gen, int stall_test, hipStream_t st);
 // Status flag and the m solve block flags of a request cleared.
-hipError_t launch_clear_flag(int* flag, int* tflag, int m, hipStream_t st);
-// io[0..5] = the request's r_fit, s_fit, r, s, coef, d (slots kIo*).
-hipError_t launch_set_io(void** io, const void* rf, const void* sf, const void* r, const void* s,
-                         double* coef, void* d, hipStream_t st);
+hipError_t launch_clear_flag(const Geom& g, int* flag, int* tflag, int m, hipStream_t st);
+// The caller buffers of the pairs of a batch: p[z] = r_fit, s_fit, r, s,
+// coef, d of pair z (slots kIo*).
+constexpr int kMaxBatch = 16;
+constexpr int kIoUsed = 6;
+struct IoBatch {
+    const void* p[kMaxBatch][kIoUsed];
+    int n;
+};
+// The I/O table of pair z (at io + z zs) := b.p[z], z < b.n.
+hipError_t launch_set_io(void** io, long long zs, const IoBatch& b, hipStream_t st);
 // dst[0..n) = src[0..n) (nothing when dst resolves to null).
-hipError_t launch_copy_f64(IoRef<double> dst, const double* src, int n, hipStream_t st);
+hipError_t launch_copy_f64(const Geom& g, IoRef<double> dst, const double* src, int n,
+                           hipStream_t st);
 
 // Subtraction.
 hipError_t launch_stamps(const Geom& g, const double* coef, double* kap, hipStream_t st);
@@ -123,5 +133,22 @@ hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<
 // kap1: scratch of (max(DK,DB) + 1 + 2 w0) * P * L1 doubles.
 hipError_t launch_sky(const Geom& g, const double* kap, const double* bcoef, const double* ped,
                       double* kap1, double* sky, hipStream_t st);
+
+// Noise decorrelation (App. C). Up to kMaxCoadd science and reference
+// images per co-add.
+constexpr int kMaxCoadd = 8;
+// st[1 + M + N][L0][L1]: the kernel at (u0, u1) from the stamps kap, then
+// the G_j (gst, or unit stamps when null) and H_i (hst, or unit stamps);
+// wts[0] = den(0), wts[s] = sigma^2 of stamp s.
+hipError_t launch_decorr_stamps(const Geom& g, const double* kap, double u0, double u1, int M,
+                                const double* sig_s, const double* gst, int N, const double* sig_r,
+                                const double* hst, double* st, double* wts, hipStream_t st_);
+// Z ([N0][hp], a row-transformed image) := column transform, times
+// Q^(l, m) / N0 from the stamps' row DFTs kr ([1 + M + N][L0][hp]), inverse
+// column transform; tw: W_N0^t, twt: pass tables.
+template <typename T>
+hipError_t launch_colconv(const Geom& g, const LinePlan& lp, cx<T>* Z, const cx<T>* kr,
+                          const double* wts, int M, int N, const cx<T>* tw, const cx<T>* twt,
+                          hipStream_t st);
 
 }  // namespace sfft

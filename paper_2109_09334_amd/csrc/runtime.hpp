@@ -157,22 +157,37 @@ struct Plan {
     Workspace ws;
     int device = 0;
     int stall_test = 0;   // triangular solves' give-up test (direct calls only)
+    // Pairs the workspace holds (g.zs bytes apart): a batch of up to cap
+    // same-variant requests runs as one launch per stage (gridDim.z = pairs).
+    int cap = 1;
     // The whole path captured once per variant -- apply pair = fit pair or
-    // not, image element type (SFFT_F32, SFFT_F64) -- with every caller
-    // buffer read from ws.io; a request then costs one table write and one
-    // graph launch. The workspace layout does not depend on the image type,
-    // so one workspace serves both, each through its own graph.
-    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    // not, image element type (SFFT_F32, SFFT_F64), pairs in the batch --
+    // with every caller buffer read from the pair's table in its workspace;
+    // a batch then costs one table write and one graph launch. The workspace
+    // layout does not depend on the image type, so one workspace serves
+    // both, each through its own graphs.
+    hipGraphExec_t graph[2][2][kMaxBatch] = {};
+    // noise decorrelation buffers (allocated on the plan's first use of it)
+    char* dec = nullptr;
+    size_t dec_bytes = 0;
 };
 
 int check_params(const sfft_params* p);
 int64_t num_unknowns(const sfft_params* p);
+Geom make_geom(const sfft_params* p);
+// Line plan of length n (radix 16 first, then 2/4/8, 3s, then 16s) and the
+// entries of its pass twiddle tables.
+LinePlan make_line_plan(int n);
+int pass_table_len(int n);
 size_t workspace_bytes(const sfft_params* p);
 int plan_run(Plan& pl, const void* rf, const void* sf, const void* r, const void* s, double* coef,
              void* d, hipStream_t st);
-// The same through the plan's captured graph (captured on first use).
-int plan_run_graph(Plan& pl, const void* rf, const void* sf, const void* r, const void* s,
-                   double* coef, void* d, hipStream_t st);
+// The io.n (<= cap) requests of a batch, one launch per stage, through the
+// plan's graph of that variant and batch size (captured on first use) or
+// launched directly (graphs = false).
+int plan_run_batch(Plan& pl, const IoBatch& io, bool same_pair, bool graphs, hipStream_t st);
+// Status flag of pair z of the plan's last batch.
+int read_pair_flag(const Plan& pl, int z, int* flag);
 int flag_status(int f);
 class Engine;
 
@@ -202,6 +217,6 @@ struct sfft_ctx {
 
 
 namespace sfft {
-int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out);
+int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out, int cap);
 void destroy_plan(sfft_ctx* ctx, std::unique_ptr<Plan>& pl);
 }  // namespace sfft

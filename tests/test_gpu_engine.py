@@ -124,12 +124,13 @@ def test_graph_replays_match_eager(sfft, prec):
                 assert torch.equal(d, dref), (prec, rep, k)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_one_workspace_alternating_image_types(sfft, prec):
+def test_one_workspace_alternating_image_types(sfft):
     """One slot, so every request reuses the same workspace: F32, F64, F32,
-    F64 requests of one geometry must each equal the direct call bit for bit
-    (each image type replays its own captured graph)."""
-    pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
+    F64 requests of one geometry (FP64 form) must each equal the direct call
+    bit for bit (each image type replays its own captured graph). The mixed
+    form refuses FP64 images at submit."""
+    prec = "fp64"
+    pr = sfft.FP64
     n0, n1, w, dk, db = 96, 128, 3, 2, 2
     R32, S32 = _inputs(7, n0, n1, w, dk, db)
     R64, S64 = R32.double(), S32.double()
@@ -150,6 +151,12 @@ def test_one_workspace_alternating_image_types(sfft, prec):
             torch.cuda.synchronize()
             assert torch.equal(c, cref), (prec, dt)
             assert torch.equal(d, dref), (prec, dt)
+        pm = sfft.Params(n0, n1, w, w, dk, db, 0, sfft.MIXED, sfft.F64)
+        c = torch.empty(pm.num_unknowns, dtype=torch.float64, device="cuda")
+        d = torch.empty((n0, n1), dtype=torch.float64, device="cuda")
+        with pytest.raises(sfft.SfftError) as ei:
+            ctx.submit(pm, R64, S64, R64, S64, c, d)
+        assert ei.value.code == sfft.E_UNSUPPORTED
 
 
 def test_submit_is_ordered_after_the_callers_stream(sfft):
@@ -183,3 +190,49 @@ def test_submit_is_ordered_after_the_callers_stream(sfft):
         torch.cuda.synchronize()
         for t, c, d in jobs:
             assert torch.equal(c, cref) and torch.equal(d, dref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_of_distinct_pairs_equals_alone(sfft, prec):
+    """One slot held by a large request while distinct same-size requests
+    queue up: they run as one batch (one launch per stage, one pair per
+    blockIdx.z), fit-pair and apply-pair variants in separate batches. Each
+    result must equal its direct call bit for bit -- with distinct inputs per
+    pair, a pair reading another pair's buffers would show."""
+    pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
+    n0, n1, w, dk, db = 96, 128, 3, 2, 2
+    p = sfft.Params(n0, n1, w, w, dk, db, 0, pr, sfft.F32)
+    big = sfft.Params(1024, 1024, 5, 5, 2, 2, 0, pr, sfft.F32)
+    Rb, Sb = _inputs(600, 1024, 1024, 5, 2, 2)
+    reqs = []
+    for k in range(11):
+        Rf, Sf = _inputs(500 + k, n0, n1, w, dk, db)
+        if k % 3 == 2:   # apply the fit to another pair of the same shape
+            R, S = _inputs(700 + k, n0, n1, w, dk, db)
+        else:
+            R, S = Rf, Sf
+        reqs.append((Rf, Sf, R, S))
+    refs = []
+    with sfft.Context(0) as eager:
+        for Rf, Sf, R, S in reqs:
+            c, d = eager.run(p, Rf, Sf, R, S)
+            eager.sync()
+            refs.append((c, d))
+    with sfft.Context(0) as ctx:
+        ctx.engine_config(1, 8)
+        for rnd in range(2):
+            cb = torch.empty(big.num_unknowns, dtype=torch.float64, device="cuda")
+            db_ = torch.empty((1024, 1024), dtype=torch.float32, device="cuda")
+            tb = ctx.submit(big, Rb, Sb, Rb, Sb, cb, db_)
+            jobs = []
+            for k, (Rf, Sf, R, S) in enumerate(reqs):
+                c = torch.full((p.num_unknowns,), float("nan"), dtype=torch.float64, device="cuda")
+                d = torch.full((n0, n1), float("nan"), dtype=torch.float32, device="cuda")
+                jobs.append((k, ctx.submit(p, Rf, Sf, R, S, c, d), c, d))
+            assert ctx.wait(tb) == sfft.OK
+            for k, t, c, d in jobs:
+                assert ctx.wait(t) == sfft.OK
+            torch.cuda.synchronize()
+            for k, t, c, d in jobs:
+                assert torch.equal(c, refs[k][0]), (prec, rnd, k)
+                assert torch.equal(d, refs[k][1]), (prec, rnd, k)

@@ -7,7 +7,9 @@ Tolerances:
   within 1e-6 relative (normwise) and D within 1e-5 of the sky noise RMS;
 * mixed form (FP32 FFTs and products, FP64 assembly / solve / one refinement
   step): the same coefficient and D tolerances after refinement; the FP32
-  normal matrix alone within 2e-5 of the largest entry.
+  normal matrix alone within 2e-5 of the largest entry. The mixed form takes
+  FP32 images and DK <= 3; other parameter sets must be refused with
+  SFFT_E_UNSUPPORTED (checked here).
 """
 import numpy as np
 import pytest
@@ -32,9 +34,10 @@ CASES = [
     # w0 != w1 (Eq. 3-4 allow independent half widths), DB > DK
     (64, 96, 2, 4, 1, 2, 0),
     (96, 64, 5, 1, 0, 3, 0),
-    # half widths without a specialised stencil (1, 6, 9, 16), DK = 3, 4
+    # half widths without a specialised stencil (1, 6, 9, 16), DK = 3, 4 (the
+    # DK = DB = 4 case on 96^2 pixels: 2536 unknowns need a well-determined fit)
     (48, 48, 1, 1, 3, 1, 0),
-    (64, 64, 6, 6, 4, 4, 1),
+    (96, 96, 6, 6, 4, 4, 1),
     # w0 >= 8 with N0 a multiple of 1024: the pruned lag pass with three and
     # five 16-lag blocks
     (1024, 48, 9, 2, 1, 1, 0),
@@ -72,6 +75,18 @@ def _params(sfft, n0, n1, w0, w1, dk, db, cp, prec, dtype):
     return sfft.Params(n0, n1, w0, w1, dk, db, cp, prec, dtype)
 
 
+def _mixed_refused(sfft, prec, dtype, dk):
+    """The parameter sets the mixed form refuses (FP64 images, DK = 4)."""
+    return prec == "mixed" and (dtype == "f64" or dk > 3)
+
+
+def _assert_refused(sfft, ctx, p, R, S):
+    assert sfft.Context.check(p) == sfft.E_UNSUPPORTED
+    with pytest.raises(sfft.SfftError) as ei:
+        ctx.run(p, R, S)
+    assert ei.value.code == sfft.E_UNSUPPORTED
+
+
 @pytest.mark.parametrize("n", [16, 48, 96, 256, 384, 1024, 4096, 6144, 8192])
 @pytest.mark.parametrize("cdt", [torch.complex128, torch.complex64])
 def test_fft_lines_vs_numpy(ctx, n, cdt):
@@ -94,8 +109,17 @@ def test_lag_tables_and_system(sfft, ctx, case, prec):
     n0, n1, w0, w1, dk, db, cp = case
     r, s = _pair(7 + n0, n0, n1, w0, dk, db, cp)
     pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
-    p = _params(sfft, n0, n1, w0, w1, dk, db, cp, pr, sfft.F64)
-    tab = ctx.lag_tables(p, _dev(r), _dev(s))
+    # the mixed form transforms FP32 images
+    dt = sfft.F64 if prec == "fp64" else sfft.F32
+    if prec == "mixed":
+        r = r.astype(np.float32).astype(np.float64)
+        s = s.astype(np.float32).astype(np.float64)
+    tdt = torch.float64 if prec == "fp64" else torch.float32
+    p = _params(sfft, n0, n1, w0, w1, dk, db, cp, pr, dt)
+    if _mixed_refused(sfft, prec, "f32", dk):
+        _assert_refused(sfft, ctx, p, _dev(r, tdt), _dev(s, tdt))
+        return
+    tab = ctx.lag_tables(p, _dev(r, tdt), _dev(s, tdt))
     om = oracle.omega(r, dk, w0, w1)
     th = oracle.theta(r, s, dk, w0, w1)
     la = oracle.lam(r, dk, db, w0, w1)
@@ -108,7 +132,7 @@ def test_lag_tables_and_system(sfft, ctx, case, prec):
     assert np.abs(tab["lambda"].cpu().numpy() - la).max() <= 1e-11 * np.abs(la).max()
     assert np.abs(tab["cmat"].cpu().numpy() - cm).max() <= 1e-12 * np.abs(cm).max()
     assert np.abs(tab["evec"].cpu().numpy() - ev).max() <= 1e-11 * np.abs(ev).max()
-    G, h = ctx.build_system(p, _dev(r), _dev(s))
+    G, h = ctx.build_system(p, _dev(r, tdt), _dev(s, tdt))
     Go, ho = oracle.build_system(r, s, w0, w1, dk, db, cp)
     Gg = G.cpu().numpy()
     assert np.array_equal(Gg, Gg.T)
@@ -132,6 +156,9 @@ def test_run_matches_oracle(sfft, ctx, case, prec, dtype):
     tdt = torch.float32 if dtype == "f32" else torch.float64
     pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
     p = _params(sfft, n0, n1, w0, w1, dk, db, cp, pr, sfft.F32 if dtype == "f32" else sfft.F64)
+    if _mixed_refused(sfft, prec, dtype, dk):
+        _assert_refused(sfft, ctx, p, _dev(r, tdt), _dev(s, tdt))
+        return
     coef, d = ctx.run(p, _dev(r, tdt), _dev(s, tdt))
     ctx.sync()
     co = oracle.fit(r, s, w0, w1, dk, db, cp)
@@ -153,8 +180,9 @@ def test_separate_calls_match_run(sfft, ctx, prec):
     n0, n1, w, dk, db, cp = 64, 96, 3, 2, 2, 0
     r, s = _pair(5, n0, n1, w, dk, db, cp)
     pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
-    p = _params(sfft, n0, n1, w, w, dk, db, cp, pr, sfft.F64)
-    R, S = _dev(r), _dev(s)
+    dt, tdt = (sfft.F64, torch.float64) if prec == "fp64" else (sfft.F32, torch.float32)
+    p = _params(sfft, n0, n1, w, w, dk, db, cp, pr, dt)
+    R, S = _dev(r, tdt), _dev(s, tdt)
     G, h = ctx.build_system(p, R, S)
     coef = ctx.solve(p, G, h, R, S)
     d = ctx.subtract(p, R, S, coef)
@@ -197,6 +225,9 @@ def test_apply_pair_differs_from_fit_pair(sfft, ctx, case, prec, dtype):
     tdt = torch.float32 if dtype == "f32" else torch.float64
     pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
     p = _params(sfft, n0, n1, w, w, dk, db, 0, pr, sfft.F32 if dtype == "f32" else sfft.F64)
+    if _mixed_refused(sfft, prec, dtype, dk):
+        _assert_refused(sfft, ctx, p, _dev(r, tdt), _dev(s, tdt))
+        return
     coef, d = ctx.run(p, _dev(rm, tdt), _dev(sm, tdt), _dev(r, tdt), _dev(s, tdt))
     ctx.sync()
     co = oracle.fit(rm, sm, w, w, dk, db)
@@ -218,16 +249,20 @@ def test_apply_pair_differs_from_fit_pair(sfft, ctx, case, prec, dtype):
 
 
 def test_config1_full(sfft, ctx):
-    """256 x 256 FP64 pair, 11 x 11 kernel, DK = DB = 0 (both forms)."""
+    """256 x 256 FP64 pair, 11 x 11 kernel, DK = DB = 0: the FP64 form on the
+    FP64 images, the mixed form on the pair rounded to FP32 (the oracle on the
+    same rounded pair)."""
     pair = datagen.config1()
-    co = oracle.fit(pair.r, pair.s, 5, 5, 0, 0)
-    do = oracle.subtract(pair.r, pair.s, co, 5, 5, 0, 0)
-    for pr in (sfft.FP64, sfft.MIXED):
-        p = sfft.Params(256, 256, 5, 5, 0, 0, 0, pr, sfft.F64)
-        coef, d = ctx.run(p, _dev(pair.r), _dev(pair.s))
+    for pr, dt, tdt in ((sfft.FP64, sfft.F64, torch.float64), (sfft.MIXED, sfft.F32, torch.float32)):
+        r = pair.r if dt == sfft.F64 else pair.r.astype(np.float32).astype(np.float64)
+        s = pair.s if dt == sfft.F64 else pair.s.astype(np.float32).astype(np.float64)
+        co = oracle.fit(r, s, 5, 5, 0, 0)
+        do = oracle.subtract(r, s, co, 5, 5, 0, 0)
+        p = sfft.Params(256, 256, 5, 5, 0, 0, 0, pr, dt)
+        coef, d = ctx.run(p, _dev(r, tdt), _dev(s, tdt))
         ctx.sync()
         assert _rel(coef.cpu().numpy(), co) <= 1e-6
-        assert np.sqrt(np.mean((d.cpu().numpy() - do) ** 2)) <= 1e-4
+        assert np.sqrt(np.mean((d.cpu().numpy().astype(np.float64) - do) ** 2)) <= 1e-4
 
 
 def test_synchronous_solve_reports_not_spd(sfft, ctx):
@@ -250,10 +285,11 @@ def test_solve_wait_give_up_is_reported(sfft):
     next normal call is unaffected."""
     n0, n1, w, dk, db = 96, 128, 3, 2, 2     # 300 unknowns: 5 blocks per sweep
     r, s = _pair(44, n0, n1, w, dk, db, 0)
-    R, S = _dev(r), _dev(s)
     with sfft.Context(0) as c:
-        for pr in (sfft.FP64, sfft.MIXED):
-            p = sfft.Params(n0, n1, w, w, dk, db, 0, pr, sfft.F64)
+        for pr, dt, tdt in ((sfft.FP64, sfft.F64, torch.float64),
+                            (sfft.MIXED, sfft.F32, torch.float32)):
+            R, S = _dev(r, tdt), _dev(s, tdt)
+            p = sfft.Params(n0, n1, w, w, dk, db, 0, pr, dt)
             cref, dref = c.run(p, R, S)
             c.sync()
             c.debug_solve_stall(True)
