@@ -154,6 +154,26 @@ int sfft_subtract(sfft_ctx* ctx, const sfft_params* p, const void* r, const void
 int sfft_run(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void* s_fit,
              const void* r, const void* s, double* coef, void* d, void* stream);
 
+/* The whole hot path of sfft_run without allocating device memory, for
+ * callers that cannot call hipMalloc (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation). Same arguments, results
+ * and apply-pair rule as sfft_run; coef may be NULL.
+ * Every buffer beyond the caller's inputs and outputs (the workspace of the
+ * geometry and the twiddle tables) is carved from one static device array
+ * of 128 MiB per GPU, held from the library's load until the process ends;
+ * a parameter set whose workspace does not fit returns SFFT_E_NOMEM before
+ * anything is enqueued (e.g. 1024 x 1024 with DK = DB = 2 fits in both
+ * precisions, 2048 x 2048 does not). Calls neither hipMalloc, hipFree nor
+ * any allocating library routine.
+ * Every call on one GPU shares that array, which keeps the last call's
+ * contents: calls that overlap on one GPU -- from any context, thread or
+ * stream -- race and give undefined results; order them on one stream.
+ * With stream == NULL the call waits for the device and returns its status
+ * (SFFT_E_NOT_SPD, SFFT_E_NONFINITE); on other streams device-side errors
+ * leave the coefficients NaN and are not reported by sfft_sync. */
+int sfft_run_noalloc(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void* s_fit,
+                     const void* r, const void* s, double* coef, void* d, void* stream);
+
 /* Noise decorrelation of a difference image (App. C, Eq. C21-C24).
  * The difference of co-adds of m_sci science images (white noise sigma_sci[j],
  * matched by the stamps g_sci[j]) and n_ref reference images (sigma_ref[i],

@@ -102,6 +102,7 @@ def lib():
             L.sfft_solve.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp]
             L.sfft_subtract.argtypes = [vp, pp, vp, vp, vp, vp, vp]
             L.sfft_run.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp, vp]
+            L.sfft_run_noalloc.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp, vp]
             dbl = ctypes.c_double
             L.sfft_decorrelate.argtypes = [vp, pp, vp, dbl, dbl, i32, vp, vp, i32, vp, vp, vp, vp, vp]
             L.sfft_sync.argtypes = [vp, vp]
@@ -118,7 +119,7 @@ def lib():
             L.sfft_strerror.argtypes = [i32]
             L.sfft_strerror.restype = ctypes.c_char_p
             for name in ("sfft_create", "sfft_check_params", "sfft_build_system", "sfft_solve",
-                         "sfft_subtract", "sfft_run", "sfft_decorrelate",
+                         "sfft_subtract", "sfft_run", "sfft_run_noalloc", "sfft_decorrelate",
                          "sfft_sync",
                          "sfft_lag_tables",
                          "sfft_fft_lines", "sfft_engine_config", "sfft_profile", "sfft_profile_read", "sfft_submit", "sfft_poll",
@@ -235,6 +236,22 @@ class Context:
                               self._img(p, s, "s"),
                               _ptr(coef, torch.float64, p.num_unknowns, "coef"),
                               self._img(p, d, "d"), _stream(stream)), "sfft_run")
+        return coef, d
+
+    def run_noalloc(self, p: Params, r_fit, s_fit, r=None, s=None, coef=None, d=None,
+                    stream=None):
+        """sfft_run_noalloc: the library allocates nothing (outputs are the
+        caller's; created here only when not given)."""
+        r = r_fit if r is None else r
+        s = s_fit if s is None else s
+        if d is None:
+            d = torch.empty((p.n0, p.n1), dtype=p.torch_dtype, device=r.device)
+        _check(lib().sfft_run_noalloc(self._h, ctypes.byref(p.c()), self._img(p, r_fit, "r_fit"),
+                                      self._img(p, s_fit, "s_fit"), self._img(p, r, "r"),
+                                      self._img(p, s, "s"),
+                                      None if coef is None else
+                                      _ptr(coef, torch.float64, p.num_unknowns, "coef"),
+                                      self._img(p, d, "d"), _stream(stream)), "sfft_run_noalloc")
         return coef, d
 
     def decorrelate(self, p: Params, coef, d, u0: float, u1: float, sigma_sci, sigma_ref,

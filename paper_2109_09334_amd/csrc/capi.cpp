@@ -705,6 +705,12 @@ int sfft_create(sfft_ctx** out, int device, size_t hbm_budget_bytes) {
     if (!c) return SFFT_E_NOMEM;
     c->device = device;
     c->budget = hbm_budget_bytes;
+    // the allocation-free entry point's scratch address on this device
+    const int rc = noalloc_init(device);
+    if (rc) {
+        delete c;
+        return rc;
+    }
     *out = c;
     return SFFT_OK;
 }
@@ -777,6 +783,15 @@ int sfft_run(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void*
     int rc = direct_plan(ctx, p, &pl);
     if (rc) return rc;
     return plan_run(*pl, r_fit, s_fit, r, s, coef, d, (hipStream_t)stream);
+}
+
+int sfft_run_noalloc(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void* s_fit,
+                     const void* r, const void* s, double* coef, void* d, void* stream) {
+    if (!ctx || !r_fit || !s_fit || !r || !s || !d) return SFFT_E_INVAL;
+    (void)hipSetDevice(ctx->device);
+    int rc = noalloc_init(ctx->device);
+    if (rc) return rc;
+    return run_noalloc(ctx->device, p, r_fit, s_fit, r, s, coef, d, (hipStream_t)stream);
 }
 
 int sfft_decorrelate(sfft_ctx* ctx, const sfft_params* p, const double* coef, double u0, double u1,

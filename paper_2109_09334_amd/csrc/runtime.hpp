@@ -189,6 +189,11 @@ int plan_run_batch(Plan& pl, const IoBatch& io, bool same_pair, bool graphs, hip
 // Status flag of pair z of the plan's last batch.
 int read_pair_flag(const Plan& pl, int z, int* flag);
 int flag_status(int f);
+// Allocation-free path (noalloc.hip): the device address of its static
+// scratch array on `device`, taken once; the whole path on that array.
+int noalloc_init(int device);
+int run_noalloc(int device, const sfft_params* p, const void* rf, const void* sf, const void* r,
+                const void* s, double* coef, void* d, hipStream_t st);
 class Engine;
 
 }  // namespace sfft
