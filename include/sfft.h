@@ -200,6 +200,31 @@ int sfft_decorrelate(sfft_ctx* ctx, const sfft_params* p, const double* coef, do
                      const double* sigma_ref, const double* h_ref, const void* d, void* out,
                      void* stream);
 
+/* Crowded-flavour preprocessing of the fit pair (Sec. 3.1): the pixels
+ * affected by saturated sources are masked and replaced by the neighbouring
+ * background, giving the masked pair to fit on (sfft_run's r_fit, s_fit)
+ * while the unmasked images stay the apply pair. The paper fixes no details;
+ * this library's reading:
+ *  - saturated: not (r < u_r and s < u_s), in the images' precision (a
+ *    non-finite pixel is saturated); a pixel is masked in both images;
+ *  - affected: within the kernel footprint of a saturated pixel, i.e. a
+ *    saturated pixel at x + (a, b) for some |a| <= g0, |b| <= g1, offsets
+ *    circular as in the convolution of Eq. 12 (g0, g1 = w0, w1 is natural);
+ *  - background: per tile of t0 x t1 pixels (the last tiles ragged), the
+ *    lower median (element (m - 1) / 2 of the m unmasked values in
+ *    ascending order); a tile with no unmasked pixel takes the lower median
+ *    of the other tiles' backgrounds, 0 if every pixel is masked;
+ *  - r_out, s_out: masked pixels := their tile's background, others copied.
+ * r, s, r_out, s_out: n0*n1 elements of dtype (SFFT_F32 / SFFT_F64); the
+ * outputs may be the inputs. mask_out: n0*n1 bytes (1 = masked) or NULL.
+ * 0 <= g0 < n0, 0 <= g1 < n1; t0 t1 <= 4096 and at most 16384 tiles
+ * (SFFT_E_UNSUPPORTED otherwise). Exact: only comparisons and selections.
+ * Stream-ordered; the context keeps a scratch of 2 n0 n1 bytes (grown on
+ * demand, after waiting for the device). */
+int sfft_crowded_mask(sfft_ctx* ctx, int n0, int n1, int dtype, const void* r, const void* s,
+                      double u_r, double u_s, int g0, int g1, int t0, int t1, void* r_out,
+                      void* s_out, unsigned char* mask_out, void* stream);
+
 /* Wait for `stream` and report device-side errors recorded since the last
  * sfft_sync on this context (SFFT_E_NOT_SPD, SFFT_E_NONFINITE) or SFFT_OK. */
 int sfft_sync(sfft_ctx* ctx, void* stream);

@@ -105,6 +105,8 @@ def lib():
             L.sfft_run_noalloc.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp, vp]
             dbl = ctypes.c_double
             L.sfft_decorrelate.argtypes = [vp, pp, vp, dbl, dbl, i32, vp, vp, i32, vp, vp, vp, vp, vp]
+            L.sfft_crowded_mask.argtypes = [vp, i32, i32, i32, vp, vp, dbl, dbl, i32, i32, i32, i32,
+                                            vp, vp, vp, vp]
             L.sfft_sync.argtypes = [vp, vp]
             L.sfft_lag_tables.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp, vp, vp]
             L.sfft_fft_lines.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp]
@@ -120,6 +122,7 @@ def lib():
             L.sfft_strerror.restype = ctypes.c_char_p
             for name in ("sfft_create", "sfft_check_params", "sfft_build_system", "sfft_solve",
                          "sfft_subtract", "sfft_run", "sfft_run_noalloc", "sfft_decorrelate",
+                         "sfft_crowded_mask",
                          "sfft_sync",
                          "sfft_lag_tables",
                          "sfft_fft_lines", "sfft_engine_config", "sfft_profile", "sfft_profile_read", "sfft_submit", "sfft_poll",
@@ -271,6 +274,24 @@ class Context:
             _ptr(h_ref, torch.float64, n * L, "h_ref"), self._img(p, d, "d"),
             self._img(p, out, "out"), _stream(stream)), "sfft_decorrelate")
         return out
+
+    def crowded_mask(self, r, s, u_r: float, u_s: float, g0: int, g1: int, t0: int = 64,
+                     t1: int = 64, r_out=None, s_out=None, want_mask: bool = False, stream=None):
+        """sfft_crowded_mask (Sec. 3.1): the masked fit pair (r_out, s_out)
+        and, with want_mask, the uint8 mask."""
+        if r.dtype not in (torch.float32, torch.float64) or s.dtype != r.dtype or r.shape != s.shape:
+            raise ValueError("r, s must be images of one shape and type (float32 or float64)")
+        n0, n1 = r.shape
+        r_out = torch.empty_like(r) if r_out is None else r_out
+        s_out = torch.empty_like(s) if s_out is None else s_out
+        m = torch.empty((n0, n1), dtype=torch.uint8, device=r.device) if want_mask else None
+        for t, nm in ((r, "r"), (s, "s"), (r_out, "r_out"), (s_out, "s_out")):
+            _ptr(t, r.dtype, n0 * n1, nm)
+        _check(lib().sfft_crowded_mask(self._h, n0, n1, F32 if r.dtype == torch.float32 else F64,
+                                       _ptr(r), _ptr(s), float(u_r), float(u_s), g0, g1, t0, t1,
+                                       _ptr(r_out), _ptr(s_out), _ptr(m, torch.uint8),
+                                       _stream(stream)), "sfft_crowded_mask")
+        return (r_out, s_out, m) if want_mask else (r_out, s_out)
 
     def sync(self, stream=None):
         _check(lib().sfft_sync(self._h, _stream(stream)), "sfft_sync")

@@ -722,6 +722,7 @@ void sfft_destroy(sfft_ctx* ctx) {
     ctx->engine.reset();
     for (auto& kv : ctx->plans) destroy_plan(ctx, kv.second);
     for (auto& kv : ctx->twid) free_twiddles(kv.second);
+    if (ctx->mbuf) (void)hipFree(ctx->mbuf);
     delete ctx;
 }
 
@@ -822,6 +823,59 @@ int sfft_decorrelate(sfft_ctx* ctx, const sfft_params* p, const double* coef, do
     }
     return SFFT_DISPATCH(*pl, run_decorr_t, coef, u0, u1, m_sci, sigma_sci, g_sci, n_ref, sigma_ref,
                          h_ref, d, out, (hipStream_t)stream);
+}
+
+int sfft_crowded_mask(sfft_ctx* ctx, int n0, int n1, int dtype, const void* r, const void* s,
+                      double u_r, double u_s, int g0, int g1, int t0, int t1, void* r_out,
+                      void* s_out, unsigned char* mask_out, void* stream) {
+    if (!ctx || !r || !s || !r_out || !s_out) return SFFT_E_INVAL;
+    if (dtype != SFFT_F32 && dtype != SFFT_F64) return SFFT_E_INVAL;
+    if (n0 < 1 || n1 < 1 || g0 < 0 || g1 < 0 || g0 >= n0 || g1 >= n1 || t0 < 1 || t1 < 1)
+        return SFFT_E_INVAL;
+    if ((long long)t0 * t1 > kMaskTileMax) return SFFT_E_UNSUPPORTED;
+    const long long ntiles = (long long)((n0 + t0 - 1) / t0) * ((n1 + t1 - 1) / t1);
+    if (ntiles > kMaskTilesMax) return SFFT_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    const size_t n = (size_t)n0 * n1;
+    Carver c;
+    unsigned char* sat = c.take<unsigned char>(nullptr, n);
+    unsigned char* tmp = c.take<unsigned char>(nullptr, n);
+    double* bg = c.take<double>(nullptr, 2 * (size_t)ntiles);
+    unsigned char* empty = c.take<unsigned char>(nullptr, 2 * (size_t)ntiles);
+    const size_t need = c.off + 256;
+    if (need > ctx->mbuf_bytes) {
+        if (ctx->budget && ctx->used - ctx->mbuf_bytes + need > ctx->budget) return SFFT_E_NOMEM;
+        if (ctx->mbuf) {
+            if (hipDeviceSynchronize() != hipSuccess) return SFFT_E_HIP;   // earlier calls may use it
+            (void)hipFree(ctx->mbuf);
+            ctx->used -= ctx->mbuf_bytes;
+            ctx->mbuf = nullptr;
+            ctx->mbuf_bytes = 0;
+        }
+        if (hipMalloc(&ctx->mbuf, need) != hipSuccess) {
+            ctx->mbuf = nullptr;
+            return SFFT_E_NOMEM;
+        }
+        ctx->mbuf_bytes = need;
+        ctx->used += need;
+    }
+    Carver c2;
+    sat = c2.take<unsigned char>(ctx->mbuf, n);
+    tmp = c2.take<unsigned char>(ctx->mbuf, n);
+    bg = c2.take<double>(ctx->mbuf, 2 * (size_t)ntiles);
+    empty = c2.take<unsigned char>(ctx->mbuf, 2 * (size_t)ntiles);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (dtype == SFFT_F32)
+        e = launch_crowded_mask<float>(n0, n1, (const float*)r, (const float*)s, u_r, u_s, g0, g1, t0,
+                                       t1, sat, tmp, reinterpret_cast<float*>(bg), empty,
+                                       (float*)r_out, (float*)s_out, mask_out, st);
+    else
+        e = launch_crowded_mask<double>(n0, n1, (const double*)r, (const double*)s, u_r, u_s, g0, g1,
+                                        t0, t1, sat, tmp, bg, empty, (double*)r_out, (double*)s_out,
+                                        mask_out, st);
+    return hip_status(e);
 }
 
 int sfft_sync(sfft_ctx* ctx, void* stream) {

@@ -134,6 +134,19 @@ hipError_t launch_stencil(const Geom& g, const cx<T>* Z, int zs_index, const cx<
 hipError_t launch_sky(const Geom& g, const double* kap, const double* bcoef, const double* ped,
                       double* kap1, double* sky, hipStream_t st);
 
+// Crowded-flavour preprocessing (Sec. 3.1): ro, so = the fit pair with the
+// pixels within (g0, g1) of a saturated pixel replaced by their t0 x t1
+// tile's lower-median background; mask_out (may be null) = the mask. sat,
+// tmp: n0 n1 bytes of scratch; bg: 2 ceil(n0/t0) ceil(n1/t1) values,
+// empty: as many bytes. t0 t1 <= kMaskTileMax, tiles <= kMaskTilesMax.
+constexpr int kMaskTileMax = 4096;
+constexpr int kMaskTilesMax = 16384;
+template <typename Tin>
+hipError_t launch_crowded_mask(int n0, int n1, const Tin* r, const Tin* s, double ur, double us,
+                               int g0, int g1, int t0, int t1, unsigned char* sat,
+                               unsigned char* tmp, Tin* bg, unsigned char* empty, Tin* ro, Tin* so,
+                               unsigned char* mask_out, hipStream_t st);
+
 // Noise decorrelation (App. C). Up to kMaxCoadd science and reference
 // images per co-add.
 constexpr int kMaxCoadd = 8;

@@ -218,6 +218,8 @@ struct sfft_ctx {
     int stall_test = 0;                                    // sfft_debug_solve_stall
     sfft::Profiler prof;
     std::unique_ptr<Engine> engine;
+    char* mbuf = nullptr;                                  // crowded-mask scratch
+    size_t mbuf_bytes = 0;
 };
 
 
