@@ -132,12 +132,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_4096_mixed.md")
 
 
 def kernel_source_hash():
-    """sha256 over the HIP/C++ sources of the library (sorted by name)."""
+    """sha256 over the device code of the library: the HIP sources (kernels
+    and their launchers) and the headers they include, sorted by name."""
     import hashlib
     d = os.path.join(ROOT, "paper_2109_09334_amd", "csrc")
     hsh = hashlib.sha256()
     for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
+        if name.endswith(".hip") or name in ("common.hpp", "fft_engine.hpp", "kernels.hpp"):
             with open(os.path.join(d, name), "rb") as f:
                 hsh.update(name.encode() + b"\0" + f.read())
     return hsh.hexdigest()
@@ -178,12 +179,18 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=32)
-    ap.add_argument("--slots", type=int, default=16,
+    ap.add_argument("--slots", type=int, default=6,
                     help="engine slots of the closed-loop served runs (4096^2 batches, C4)")
     ap.add_argument("--stream-slots", type=int, default=4,
                     help="engine slots of the C5 stream (latency under load)")
-    ap.add_argument("--max-batch", type=int, default=4,
+    ap.add_argument("--max-batch", type=int, default=8,
                     help="requests of one variant the engine runs as one launch per stage")
+    ap.add_argument("--stream-max-batch", type=int, default=4,
+                    help="the same for the C5 stream's engine")
+    ap.add_argument("--hbm-budget-gb", type=float, default=96.0,
+                    help="HBM budget of the closed-loop engine (idle workspaces are evicted to fit)")
+    ap.add_argument("--stream-hbm-budget-gb", type=float, default=160.0,
+                    help="HBM budget of the C5 stream's engine")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--stars", type=int, default=40000)
     ap.add_argument("--stream-requests", type=int, default=2000,
@@ -195,7 +202,7 @@ def main():
     ap.add_argument("--c4-reps", type=int, default=5, help="repetitions of the C4 batch (median)")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help=argparse.SUPPRESS)   # internal: the oracle on an N x N crop
-    ap.add_argument("--mix-batch", type=int, default=48,
+    ap.add_argument("--mix-batch", type=int, default=400,
                     help="requests of the closed-loop run that sets the saturated rate of the mix")
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--no-c4", action="store_true")
@@ -204,7 +211,8 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="run N device copies of 1 GiB (calibrates HBM counters) and exit")
     ap.add_argument("--single", action="store_true",
-                    help="two direct mixed-form runs of the workload (for profilers) and exit")
+                    help="two direct mixed-form runs of a batch of --max-batch distinct pairs of the "
+                         "workload (the launches the stage rooflines time; for profilers) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -249,15 +257,24 @@ def main():
 
     n, w, dk, db = args.size, 7, 2, 2
     if args.single:
+        # the launches the stage rooflines are measured on: a batch of
+        # max_batch distinct pairs, one launch per stage, run twice
         r_np, s_np = load_pair(n, args.stars)
         R = torch.from_numpy(r_np).to("cuda")
         S = torch.from_numpy(s_np).to("cuda")
         ctx = sf.Context(0)
         p = sf.Params(n, n, w, w, dk, db, 0, sf.MIXED, sf.F32)
+        rng = np.random.default_rng(31)
+        items = []
+        for k in range(max(1, args.max_batch)):
+            a, b = (0, 0) if k == 0 else (int(v) for v in rng.integers(1, n, 2))
+            R_ = torch.roll(R, (a, b), (0, 1)).contiguous()
+            S_ = torch.roll(S, (a, b), (0, 1)).contiguous()
+            items.append((R_, S_, R_, S_, None, torch.empty((n, n), device="cuda")))
         for i in range(2):
-            ctx.run(p, R, S)
+            ctx.run_batch(p, items)
             ctx.sync()
-            log(f"[bench] single run {i + 1}/2")
+            log(f"[bench] direct batch of {len(items)}: run {i + 1}/2")
         ctx.close()
         return
     t0 = time.time()
@@ -267,10 +284,11 @@ def main():
     R = torch.from_numpy(r_np).to(dev)
     S = torch.from_numpy(s_np).to(dev)
     ctx = sf.Context(0)           # direct per-stage calls
-    srv = sf.Context(0)           # closed-loop served runs: --slots
+    budget = int(args.hbm_budget_gb * 2 ** 30)
+    srv = sf.Context(0, budget)   # closed-loop served runs: --slots
     srv.engine_config(args.slots, args.max_batch)
-    strm = sf.Context(0)          # the C5 stream: --stream-slots
-    strm.engine_config(args.stream_slots, args.max_batch)
+    strm = sf.Context(0, int(args.stream_hbm_budget_gb * 2 ** 30))   # the C5 stream
+    strm.engine_config(args.stream_slots, args.stream_max_batch)
     pm = sf.Params(n, n, w, w, dk, db, 0, sf.MIXED, sf.F32)
     p64 = sf.Params(n, n, w, w, dk, db, 0, sf.FP64, sf.F32)
     nu = pm.num_unknowns
@@ -461,21 +479,37 @@ def main():
         log(f"[bench] C4 batch: {c4['pairs_per_s']:.1f} pairs/s")
 
     # ---- per-stage HIP-event times of direct calls (same stream as the kernels)
-    def stages(p, iters=3):
-        c = torch.empty(nu, dtype=torch.float64, device=dev)
-        d = torch.empty((n, n), dtype=torch.float32, device=dev)
-        ctx.run(p, R, S, R, S, c, d)
+    def stages(p, iters=3, batch=1):
+        """ms per call of every stage: one pair (sfft_run) or a batch of
+        distinct pairs as one launch per stage (sfft_run_batch)."""
+        items = []
+        for k in range(batch):
+            R_, S_ = pairs_c3[k % len(pairs_c3)]
+            items.append((R_, S_, R_, S_, torch.empty(nu, dtype=torch.float64, device=dev),
+                          torch.empty((n, n), dtype=torch.float32, device=dev)))
+
+        def call():
+            if batch == 1:
+                ctx.run(p, *items[0])
+            else:
+                ctx.run_batch(p, items)
+
+        call()
         ctx.sync()
         ctx.profile(True)
         for _ in range(iters):
-            ctx.run(p, R, S, R, S, c, d)
+            call()
         ctx.sync()
         out = {k: v[0] / v[1] for k, v in ctx.profile_read().items()}
         ctx.profile(False)
         return out
 
+    nbat = max(1, args.max_batch)
     st_m = stages(pm)
     st_64 = stages(p64) if not args.no_fp64 else None
+    st_mb = stages(pm, batch=nbat)
+    log(f"[bench] stages of a batch of {nbat}: " +
+        ", ".join(f"{k} {v:.3f}" for k, v in st_mb.items()))
 
     # ---- noise decorrelation (App. C) of the served difference image
     def decorr_ms(p, coef, d, iters=5):
@@ -494,15 +528,18 @@ def main():
     dec_ms = decorr_ms(pm, coef_m, d_m)
     log(f"[bench] decorrelation: {dec_ms:.3f} ms")
     geo = {"n0": n, "n1": n, "w": w, "dk": dk, "db": db}
-    # every stage against its own roofline (algorithmic bytes / flops per call
-    # over the HIP-event time of the call); the reported roofline is that of
-    # the stage with the largest time per pair
+    # every stage against its own roofline: algorithmic bytes / flops of the
+    # pairs one launch set serves over the HIP-event time of that set, for the
+    # batch the engine serves with (max_batch distinct pairs per launch); the
+    # reported roofline is that of the stage with the largest time per pair
     stage_roof = {}
-    for name, ms in st_m.items():
+    for name, ms in st_mb.items():
         wk = stage_work(geo, name, 8)
         if wk is not None:
-            stage_roof[name] = roofline(name, ms, wk)
-    dom = max(stage_roof.values(), key=lambda r: r["kernel_ms"])
+            stage_roof[name] = roofline(name, ms, (wk[0] * nbat, wk[1] * nbat))
+            stage_roof[name]["pairs_per_launch"] = nbat
+            stage_roof[name]["ms_per_pair"] = ms / nbat
+    dom = max(stage_roof.values(), key=lambda r: r["ms_per_pair"])
     roof = dict(dom)
     roof["traffic"] = measured_traffic(dom["kernel"])
 
@@ -579,6 +616,9 @@ def main():
                                f"15x15 kernel (w=7), DK=2, DB=2, {nu} unknowns",
                    "precision": "mixed: FP32 FFTs/products, FP64 lags/assembly/Cholesky/refinement",
                    "batch_per_step": args.batch, "engine_slots": args.slots,
+                   "max_batch": args.max_batch, "stream_max_batch": args.stream_max_batch,
+                   "hbm_budget_gb": args.hbm_budget_gb,
+                   "stream_hbm_budget_gb": args.stream_hbm_budget_gb,
                    "stream_engine_slots": args.stream_slots,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "p50_latency_ms": stream["mixed"]["loads"]["0.8"]["p50_ms"] if stream else None,
@@ -591,7 +631,7 @@ def main():
                               "frac": thr_m * balg / 1e9 / HBM_PEAK_GBS},
         "fp64_form": res64,
         "vs_oracle": vs_oracle,
-        "stages_ms": {"mixed": st_m, "fp64": st_64},
+        "stages_ms": {"mixed": st_m, "fp64": st_64, f"mixed_batch_of_{nbat}": st_mb},
         "roofline": roof,
         "stage_roofline": stage_roof,
         "decorrelation": {"ms": dec_ms, "roofline": roofline("decorrelate", dec_ms,

@@ -291,6 +291,17 @@ typedef struct {
     void* stream;
 } sfft_request;
 
+/* n requests (1 <= n <= 16) of one variant -- identical params, and the
+ * apply pair equal to the fit pair in all of them or in none -- as one
+ * batch: every stage of sfft_run is one launch for all of them (the pair
+ * selected by blockIdx.z), on the context's workspace of that geometry
+ * (grown to hold n pairs, after waiting for the device, if it holds fewer).
+ * Each pair's result equals sfft_run on it, bit for bit. The requests'
+ * own stream fields are ignored: the batch is ordered on `stream`; device
+ * errors of any pair are reported by sfft_sync. Stage timers (sfft_profile)
+ * time the batch's launches. */
+int sfft_run_batch(sfft_ctx* ctx, const sfft_request* reqs, int n, void* stream);
+
 /* Configure the engine: `slots` concurrent batches (each on its own HIP
  * stream with its own workspace), each of up to `max_batch` requests
  * (<= 16) of one variant -- the same parameters and image type, and the

@@ -103,6 +103,7 @@ def lib():
             L.sfft_subtract.argtypes = [vp, pp, vp, vp, vp, vp, vp]
             L.sfft_run.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp, vp]
             L.sfft_run_noalloc.argtypes = [vp, pp, vp, vp, vp, vp, vp, vp, vp]
+            L.sfft_run_batch.argtypes = [vp, ctypes.POINTER(_Request), i32, vp]
             dbl = ctypes.c_double
             L.sfft_decorrelate.argtypes = [vp, pp, vp, dbl, dbl, i32, vp, vp, i32, vp, vp, vp, vp, vp]
             L.sfft_crowded_mask.argtypes = [vp, i32, i32, i32, vp, vp, dbl, dbl, i32, i32, i32, i32,
@@ -121,7 +122,7 @@ def lib():
             L.sfft_strerror.argtypes = [i32]
             L.sfft_strerror.restype = ctypes.c_char_p
             for name in ("sfft_create", "sfft_check_params", "sfft_build_system", "sfft_solve",
-                         "sfft_subtract", "sfft_run", "sfft_run_noalloc", "sfft_decorrelate",
+                         "sfft_subtract", "sfft_run", "sfft_run_noalloc", "sfft_run_batch", "sfft_decorrelate",
                          "sfft_crowded_mask",
                          "sfft_sync",
                          "sfft_lag_tables",
@@ -240,6 +241,18 @@ class Context:
                               _ptr(coef, torch.float64, p.num_unknowns, "coef"),
                               self._img(p, d, "d"), _stream(stream)), "sfft_run")
         return coef, d
+
+    def run_batch(self, p: Params, items, stream=None):
+        """sfft_run_batch: items = [(r_fit, s_fit, r, s, coef or None, d)],
+        all of variant p, as one launch per stage."""
+        n = len(items)
+        arr = (_Request * n)()
+        for z, (rf, sf, r, s, coef, d) in enumerate(items):
+            arr[z] = _Request(p.c(), self._img(p, rf, "r_fit"), self._img(p, sf, "s_fit"),
+                              self._img(p, r, "r"), self._img(p, s, "s"),
+                              _ptr(coef, torch.float64, p.num_unknowns, "coef") if coef is not None
+                              else None, self._img(p, d, "d"), None)
+        _check(lib().sfft_run_batch(self._h, arr, n, _stream(stream)), "sfft_run_batch")
 
     def run_noalloc(self, p: Params, r_fit, s_fit, r=None, s=None, coef=None, d=None,
                     stream=None):

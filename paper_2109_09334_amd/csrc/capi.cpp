@@ -224,7 +224,8 @@ static size_t pair_stride(const sfft_params* p) { return (workspace_bytes(p) + 2
 
 // Allocate a plan (with the workspaces of `cap` pairs) against the context
 // budget. Caller holds ctx->mu.
-int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out, int cap) {
+int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out, int cap,
+                hipStream_t init_stream) {
     int rc = check_params(p);
     if (rc) return rc;
     if (cap < 1 || cap > kMaxBatch) return SFFT_E_INVAL;
@@ -250,10 +251,12 @@ int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out,
     // 1-D polynomial sums depend on the geometry only: formed once here.
     Geom all = pl->g;
     all.nb = cap;
-    if (launch_clear_flag(all, pl->ws.flag, pl->ws.tflag, tflag_len(all), nullptr) != hipSuccess ||
-        launch_polysum(all, poly_degree(all), pl->ws.sig0, pl->ws.sig1, pl->ws.pw, nullptr) !=
+    // (on init_stream, ahead of the plan's first use there; on the null
+    // stream, waited for, when none is given)
+    if (launch_clear_flag(all, pl->ws.flag, pl->ws.tflag, tflag_len(all), init_stream) != hipSuccess ||
+        launch_polysum(all, poly_degree(all), pl->ws.sig0, pl->ws.sig1, pl->ws.pw, init_stream) !=
             hipSuccess ||
-        hipStreamSynchronize(nullptr) != hipSuccess) {
+        (!init_stream && hipStreamSynchronize(nullptr) != hipSuccess)) {
         (void)hipFree(base);
         return SFFT_E_HIP;
     }
@@ -277,14 +280,24 @@ void destroy_plan(sfft_ctx* ctx, std::unique_ptr<Plan>& pl) {
     pl.reset();
 }
 
-static int direct_plan(sfft_ctx* ctx, const sfft_params* p, Plan** out) {
+// The context's plan of p with room for `pairs` pairs (a plan with less is
+// replaced, after the device has finished with it).
+static int direct_plan(sfft_ctx* ctx, const sfft_params* p, Plan** out, int pairs = 1) {
     int rc = check_params(p);
     if (rc) return rc;
     auto k = key_of(p);
     auto it = ctx->plans.find(k);
+    if (it != ctx->plans.end() && it->second->cap < pairs) {
+        if (hipDeviceSynchronize() != hipSuccess) return SFFT_E_HIP;
+        destroy_plan(ctx, it->second);
+        ctx->plans.erase(it);
+        it = ctx->plans.end();
+    }
     if (it == ctx->plans.end()) {
         std::unique_ptr<Plan> pl;
-        rc = create_plan(ctx, p, pl, 1);
+        int cap = 1;
+        while (cap < pairs) cap *= 2;
+        rc = create_plan(ctx, p, pl, cap);
         if (rc) return rc;
         it = ctx->plans.emplace(k, std::move(pl)).first;
     }
@@ -654,7 +667,7 @@ int plan_run_batch(Plan& pl, const IoBatch& io, bool same_pair, bool graphs, hip
     hipError_t e = launch_set_io(pl.ws.io, pl.g.zs, io, st);
     if (e) return SFFT_E_HIP;
     Profiler* saved = pl.prof;
-    pl.prof = nullptr;   // no timing events inside a batch
+    if (graphs) pl.prof = nullptr;   // no timing events inside a graph
     int rc = SFFT_OK;
     pl.g.nb = b;
     if (!graphs) {
@@ -885,13 +898,38 @@ int sfft_sync(sfft_ctx* ctx, void* stream) {
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SFFT_E_HIP;
     int all = 0;
     for (auto& kv : ctx->plans) {
-        int f = 0;
-        if (hipMemcpy(&f, kv.second->ws.flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
-            return SFFT_E_HIP;
-        all |= f;
-        if (f) (void)hipMemset(kv.second->ws.flag, 0, sizeof(int));
+        for (int z = 0; z < kv.second->cap; ++z) {   // every pair of a batch
+            int f = 0;
+            if (read_pair_flag(*kv.second, z, &f) != SFFT_OK) return SFFT_E_HIP;
+            all |= f;
+            char* fz = reinterpret_cast<char*>(kv.second->ws.flag) + (size_t)z * kv.second->g.zs;
+            if (f) (void)hipMemset(fz, 0, sizeof(int));
+        }
     }
     return flag_status(all);
+}
+
+int sfft_run_batch(sfft_ctx* ctx, const sfft_request* reqs, int n, void* stream) {
+    if (!ctx || !reqs || n < 1) return SFFT_E_INVAL;
+    if (n > kMaxBatch) return SFFT_E_UNSUPPORTED;
+    const sfft_params& p0 = reqs[0].p;
+    const bool same = reqs[0].r == reqs[0].r_fit && reqs[0].s == reqs[0].s_fit;
+    IoBatch io{};
+    io.n = n;
+    for (int z = 0; z < n; ++z) {
+        const sfft_request& q = reqs[z];
+        if (!q.r_fit || !q.s_fit || !q.r || !q.s || !q.d) return SFFT_E_INVAL;
+        if (std::memcmp(&q.p, &p0, sizeof(sfft_params)) != 0) return SFFT_E_INVAL;
+        if ((q.r == q.r_fit && q.s == q.s_fit) != same) return SFFT_E_INVAL;
+        const void* ptrs[kIoUsed] = {q.r_fit, q.s_fit, q.r, q.s, q.coef, q.d};
+        for (int k = 0; k < kIoUsed; ++k) io.p[z][k] = ptrs[k];
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    Plan* pl;
+    int rc = direct_plan(ctx, &p0, &pl, n);
+    if (rc) return rc;
+    return plan_run_batch(*pl, io, same, false, (hipStream_t)stream);
 }
 
 int sfft_lag_tables(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void* s_fit,

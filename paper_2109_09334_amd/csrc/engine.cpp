@@ -110,7 +110,7 @@ static int pow2_at_least(int n) {
 // geometry with the least room that holds them, else a new one (room for
 // the next power of two, at most max_batch) within the budget, evicting
 // idle workspaces of other geometries. Caller holds mu_.
-int Engine::acquire(const sfft_params& p, int pairs, std::unique_ptr<Plan>& out,
+int Engine::acquire(const sfft_params& p, int pairs, hipStream_t st, std::unique_ptr<Plan>& out,
                     bool* wait_for_memory) {
     *wait_for_memory = false;
     auto key = key_of(&p);
@@ -127,6 +127,18 @@ int Engine::acquire(const sfft_params& p, int pairs, std::unique_ptr<Plan>& out,
     std::lock_guard<std::mutex> ck(ctx_->mu);
     const int cap = std::min(pow2_at_least(pairs), max_batch_);
     const size_t need = ((workspace_bytes(&p) + 255) & ~size_t(255)) * cap;
+    // an idle workspace of this geometry with less room is taken (the batch
+    // shrinks to it) rather than evicting others to make a bigger one
+    if (ctx_->budget && ctx_->used + need > ctx_->budget) {
+        auto big = idle_.end();
+        for (auto it = range.first; it != range.second; ++it)
+            if (big == idle_.end() || it->second->cap > big->second->cap) big = it;
+        if (big != idle_.end()) {
+            out = std::move(big->second);
+            idle_.erase(big);
+            return SFFT_OK;
+        }
+    }
     while (ctx_->budget && ctx_->used + need > ctx_->budget && !idle_.empty()) {
         auto victim = idle_.begin();
         destroy_plan(ctx_, victim->second);
@@ -136,7 +148,17 @@ int Engine::acquire(const sfft_params& p, int pairs, std::unique_ptr<Plan>& out,
         *wait_for_memory = true;
         return SFFT_E_NOMEM;
     }
-    return create_plan(ctx_, &p, out, cap);
+    int rc = create_plan(ctx_, &p, out, cap, st);
+    // the device itself out of memory: free idle workspaces, then wait for
+    // running requests to return theirs
+    while (rc == SFFT_E_NOMEM && !idle_.empty()) {
+        auto victim = idle_.begin();
+        destroy_plan(ctx_, victim->second);
+        idle_.erase(victim);
+        rc = create_plan(ctx_, &p, out, cap, st);
+    }
+    if (rc == SFFT_E_NOMEM) *wait_for_memory = true;
+    return rc;
 }
 
 void Engine::loop() {
@@ -174,10 +196,10 @@ void Engine::loop() {
                 if (same_variant(queue_[i].req, queue_[0].req)) pick.push_back(i);
             std::unique_ptr<Plan> pl;
             bool wait_mem = false;
-            int rc = acquire(queue_[0].req.p, (int)pick.size(), pl, &wait_mem);
+            int rc = acquire(queue_[0].req.p, (int)pick.size(), free_slot->st, pl, &wait_mem);
             if (rc && wait_mem && pick.size() > 1) {   // the head alone may still fit
                 pick.resize(1);
-                rc = acquire(queue_[0].req.p, 1, pl, &wait_mem);
+                rc = acquire(queue_[0].req.p, 1, free_slot->st, pl, &wait_mem);
             }
             if (rc && wait_mem && running) break;       // memory frees as requests finish
             if (rc) {

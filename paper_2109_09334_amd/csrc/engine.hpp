@@ -53,7 +53,8 @@ private:
         std::unique_ptr<Plan> plan;
     };
     void loop();
-    int acquire(const sfft_params& p, int pairs, std::unique_ptr<Plan>& out, bool* wait_for_memory);
+    int acquire(const sfft_params& p, int pairs, hipStream_t st, std::unique_ptr<Plan>& out,
+                bool* wait_for_memory);
     hipEvent_t take_event();   // caller holds mu_
 
     sfft_ctx* ctx_;

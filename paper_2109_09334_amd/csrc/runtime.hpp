@@ -224,6 +224,9 @@ struct sfft_ctx {
 
 
 namespace sfft {
-int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out, int cap);
+// Plan of p with the workspaces of `cap` pairs; its initialisation kernels
+// run on init_stream (nullptr: the null stream, waited for).
+int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out, int cap,
+                hipStream_t init_stream = nullptr);
 void destroy_plan(sfft_ctx* ctx, std::unique_ptr<Plan>& pl);
 }  // namespace sfft

@@ -236,3 +236,63 @@ def test_batch_of_distinct_pairs_equals_alone(sfft, prec):
             for k, t, c, d in jobs:
                 assert torch.equal(c, refs[k][0]), (prec, rnd, k)
                 assert torch.equal(d, refs[k][1]), (prec, rnd, k)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_direct_batch_equals_each_run(sfft, prec):
+    """sfft_run_batch: n distinct pairs of one variant as one launch per stage
+    on the context's workspace; each result equals sfft_run on it bit for
+    bit, for n = 5 (a workspace of 8 pairs) and then n = 3 on the same
+    workspace, both apply-pair variants."""
+    pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
+    n0, n1, w, dk, db = 96, 128, 3, 2, 2
+    p = sfft.Params(n0, n1, w, w, dk, db, 0, pr, sfft.F32)
+    with sfft.Context(0) as ctx:
+        for n, same in ((5, True), (3, False), (5, False)):
+            items, refs = [], []
+            for k in range(n):
+                Rf, Sf = _inputs(800 + 10 * n + k, n0, n1, w, dk, db)
+                R, S = (Rf, Sf) if same else _inputs(900 + 10 * n + k, n0, n1, w, dk, db)
+                cr, dr = ctx.run(p, Rf, Sf, R, S)
+                ctx.sync()
+                refs.append((cr.clone(), dr.clone()))
+                c = torch.full((p.num_unknowns,), float("nan"), dtype=torch.float64, device="cuda")
+                d = torch.full((n0, n1), float("nan"), dtype=torch.float32, device="cuda")
+                items.append((Rf, Sf, R, S, c, d))
+            ctx.run_batch(p, items)
+            ctx.sync()
+            for k, it in enumerate(items):
+                assert torch.equal(it[4], refs[k][0]), (prec, n, same, k)
+                assert torch.equal(it[5], refs[k][1]), (prec, n, same, k)
+
+
+def test_direct_batch_reports_a_bad_pair(sfft):
+    """A pair whose normal matrix is singular inside a batch: sfft_sync
+    reports it, its coefficients are NaN, the other pairs are unaffected."""
+    n0 = n1 = 32
+    p = sfft.Params(n0, n1, 1, 1, 0, 0, 0, sfft.FP64, sfft.F64)
+    rng = torch.Generator(device="cpu").manual_seed(5)
+    good = [(torch.randn(n0, n1, generator=rng, dtype=torch.float64).cuda() + 100.0,
+             torch.randn(n0, n1, generator=rng, dtype=torch.float64).cuda() + 100.0) for _ in range(3)]
+    zero = torch.zeros((n0, n1), dtype=torch.float64, device="cuda")
+    one = torch.ones((n0, n1), dtype=torch.float64, device="cuda")
+    pairs = [good[0], (zero, one), good[1], good[2]]
+    with sfft.Context(0) as ctx:
+        refs = []
+        for R, S in pairs:
+            c, d = ctx.run(p, R, S)
+            try:
+                ctx.sync()
+            except sfft.SfftError:
+                pass
+            refs.append(c.clone())
+        items = [(R, S, R, S, torch.empty(p.num_unknowns, dtype=torch.float64, device="cuda"),
+                  torch.empty((n0, n1), dtype=torch.float64, device="cuda")) for R, S in pairs]
+        ctx.run_batch(p, items)
+        with pytest.raises(sfft.SfftError) as ei:
+            ctx.sync()
+        assert ei.value.code == sfft.E_NOT_SPD
+        assert torch.isnan(items[1][4]).all()
+        for k in (0, 2, 3):
+            assert torch.equal(items[k][4], refs[k])
+        ctx.sync()   # reported once
