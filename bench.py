@@ -478,6 +478,41 @@ def main():
     if c4:
         log(f"[bench] C4 batch: {c4['pairs_per_s']:.1f} pairs/s")
 
+    def decam_shape(reps=3):
+        """The paper's DECam CCD shape (2046 x 4094, Sec. 5 / Table 2), whose
+        lengths need Bluestein lines: w = 8 (twice the seeing FWHM), DK = DB =
+        2, mixed form, 32 requests over 8 distinct resident pairs served
+        through the closed-loop engine; per-pair wall time."""
+        n0_, n1_, w_ = 2046, 4094, 8
+        pr = cached_pair("decam", lambda: datagen.star_pair(2046, n0_, n1_, w=w_, dk=2, db=2))
+        base = copies(torch.from_numpy(pr[0]).to(dev), torch.from_numpy(pr[1]).to(dev), 8, 2046)
+        p = sf.Params(n0_, n1_, w_, w_, 2, 2, 0, sf.MIXED, sf.F32)
+        outs = [(torch.empty(p.num_unknowns, dtype=torch.float64, device=dev),
+                 torch.empty((n0_, n1_), dtype=torch.float32, device=dev)) for _ in range(32)]
+
+        def once():
+            tk = [srv.submit(p, *base[k % 8], *base[k % 8], *o) for k, o in enumerate(outs)]
+            for x in tk:
+                srv.wait(x)
+            torch.cuda.synchronize()
+
+        once()
+        times = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            once()
+            times.append(time.perf_counter() - t)
+        dt = float(np.median(times)) / 32
+        return {"workload": f"{n0_}x{n1_} FP32 pair, 17x17 kernel (w=8), DK=DB=2, "
+                            f"{p.num_unknowns} unknowns, mixed form, Bluestein lines on both axes",
+                "pairs_per_s": 1.0 / dt, "ms_per_pair": 1e3 * dt, "reps": reps,
+                "paper_context": "SFFT subtraction 1.61 s/pair on a V100, 0.97 s/pair on an A100 "
+                                 "(Table 2, 2046x4094 DECam CCDs, sparse flavour)"}
+
+    decam = None if args.no_c4 else decam_shape()
+    if decam:
+        log(f"[bench] DECam shape: {decam['pairs_per_s']:.1f} pairs/s")
+
     # ---- per-stage HIP-event times of direct calls (same stream as the kernels)
     def stages(p, iters=3, batch=1):
         """ms per call of every stage: one pair (sfft_run) or a batch of
@@ -627,6 +662,7 @@ def main():
                         "arrivals at 0.8 x the saturated rate of the mix, mixed form",
         "stream": stream,
         "c4_batch": c4,
+        "decam_shape": decam,
         "pipeline_roofline": {"bytes_per_pair": balg, "achieved_gbs": thr_m * balg / 1e9,
                               "frac": thr_m * balg / 1e9 / HBM_PEAK_GBS},
         "fp64_form": res64,

@@ -32,12 +32,16 @@
  *    skipping (k > 0, a = b = 0) when const_phot_ratio is set; then the
  *    background terms (p, q) in the same order. Coefficients are the
  *    pixel-unit a-ring of Eq. 13 (a = N0 N1 a-ring).
- *  - Supported sizes: n0, n1 = 2^a 3^b, multiples of 16, 16 <= n <= 8192;
+ *  - Supported sizes: even n0, n1 >= 16; lengths 2^a 3^b that are multiples
+ *    of 16 up to 8192 are transformed directly, other lengths up to 4096
+ *    (e.g. the 2046 x 4094 DECam CCDs of Sec. 5) by Bluestein's chirp-z
+ *    transform of a power-of-two length (every result the same DFT);
  *    4 w + 1 <= n; 0 <= DK, DB <= 4; w0, w1 <= 16. SFFT_MIXED takes FP32
- *    images and DK <= 3 (SFFT_E_UNSUPPORTED otherwise): FP64 images would be
- *    rounded to FP32 before its transforms, a perturbation its refinement
- *    step cannot correct, and at DK = 4 its coefficients stay 2-4e-6 from
- *    the FP64 optimum; those run in SFFT_FP64.
+ *    images, DK <= 3 and sides of at least 48 pixels (SFFT_E_UNSUPPORTED
+ *    otherwise): FP64 images would be rounded to FP32 before its transforms,
+ *    a perturbation its refinement step cannot correct, and at DK = 4 or on
+ *    narrower strips its coefficients stay 0.7-4e-6 from the FP64 optimum;
+ *    those run in SFFT_FP64.
  *
  * Memory and streams: every image, matrix and vector argument is a device
  * pointer owned by the caller (for instance the storage of a PyTorch
@@ -72,7 +76,7 @@ enum {
     SFFT_E_NOMEM = -2,         /* workspace does not fit the HBM budget */
     SFFT_E_NOT_SPD = -3,       /* normal matrix not positive definite */
     SFFT_E_NONFINITE = -4,     /* NaN or Inf in the inputs / normal matrix */
-    SFFT_E_UNSUPPORTED = -5,   /* size not of the form 2^a 3^b, too large, ... */
+    SFFT_E_UNSUPPORTED = -5,   /* odd or too large a size, parameters out of range */
     SFFT_E_HIP = -6,           /* HIP runtime error */
     SFFT_E_NOTFOUND = -7       /* unknown request ticket */
 };
@@ -161,8 +165,9 @@ int sfft_run(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, const void*
  * Every buffer beyond the caller's inputs and outputs (the workspace of the
  * geometry and the twiddle tables) is carved from one static device array
  * of 128 MiB per GPU, held from the library's load until the process ends;
- * a parameter set whose workspace does not fit returns SFFT_E_NOMEM before
- * anything is enqueued (e.g. 1024 x 1024 with DK = DB = 2 fits in both
+ * a parameter set whose workspace does not fit returns SFFT_E_NOMEM, and one
+ * with a Bluestein length (see the supported sizes) SFFT_E_UNSUPPORTED,
+ * before anything is enqueued (e.g. 1024 x 1024 with DK = DB = 2 fits in both
  * precisions, 2048 x 2048 does not). Calls neither hipMalloc, hipFree nor
  * any allocating library routine.
  * Every call on one GPU shares that array, which keeps the last call's
@@ -239,7 +244,9 @@ int sfft_lag_tables(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, cons
 
 /* Batched complex line transform of the library's FFT engine (diagnostics):
  * `lines` lines of n complex values (interleaved re, im of `dtype`),
- * contiguous; sign -1 forward (e^-), +1 unnormalised inverse. */
+ * contiguous; sign -1 forward (e^-), +1 unnormalised inverse. Any n >= 2
+ * whose transform length fits 8192 (Bluestein lines for lengths other than
+ * multiples of 16 of the form 2^a 3^b). */
 int sfft_fft_lines(sfft_ctx* ctx, int n, int lines, int sign, int dtype, const void* in, void* out,
                    void* stream);
 

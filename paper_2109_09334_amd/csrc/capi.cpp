@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -24,6 +25,7 @@ namespace sfft {
 static int nterms(int d) { return (d + 1) * (d + 2) / 2; }
 
 constexpr int kMaxMixedDegree = 3;   // largest DK of the mixed form
+constexpr int kMinMixedSide = 48;    // shortest image side of the mixed form
 
 static bool radix23(int n, int* a2, int* a3) {
     int a = 0, b = 0;
@@ -33,6 +35,21 @@ static bool radix23(int n, int* a2, int* a3) {
     *a3 = b;
     return n == 1;
 }
+
+// A line length the radix-16/8/4/2/3 passes transform directly.
+static bool direct_length(int n) {
+    int a, b;
+    return n >= 16 && n % 16 == 0 && radix23(n, &a, &b);
+}
+
+// Bluestein transform length of a line of n points: the power of two >= 2n - 1.
+static int bluestein_length(int n) {
+    int m = 16;
+    while (m < 2 * n - 1) m *= 2;
+    return m;
+}
+
+constexpr int kMaxLine = 8192;   // longest transform of the line engine
 
 int check_params(const sfft_params* p) {
     if (!p) return SFFT_E_INVAL;
@@ -46,13 +63,19 @@ int check_params(const sfft_params* p) {
     // The mixed form transforms FP32 data. FP64 images would be rounded to
     // FP32 before the transforms, a perturbation of the problem that the
     // refinement step cannot see (its difference image comes from the same
-    // rounded transforms), and DK = 4 leaves the FP32 path's fixed point
-    // 2-4e-6 from the FP64 optimum: both run in the FP64 form.
-    if (p->precision == SFFT_MIXED && (p->dtype != SFFT_F32 || p->dk > kMaxMixedDegree))
+    // rounded transforms); DK = 4 leaves the FP32 path's fixed point 2-4e-6
+    // from the FP64 optimum, and strips narrower than 48 pixels come close to
+    // that (the background block, 0.7-3e-6 on 32-34 pixel strips): these run
+    // in the FP64 form.
+    if (p->precision == SFFT_MIXED &&
+        (p->dtype != SFFT_F32 || p->dk > kMaxMixedDegree || p->n0 < kMinMixedSide ||
+         p->n1 < kMinMixedSide))
         return SFFT_E_UNSUPPORTED;
-    int a, b;
+    // lengths 2^a 3^b (multiples of 16) are transformed directly, other even
+    // lengths by Bluestein's chirp transform of a power-of-two length
     for (int n : {p->n0, p->n1}) {
-        if (n % 16 || n > 8192 || !radix23(n, &a, &b)) return SFFT_E_UNSUPPORTED;
+        if (n % 2) return SFFT_E_UNSUPPORTED;
+        if (direct_length(n) ? n > kMaxLine : bluestein_length(n) > kMaxLine) return SFFT_E_UNSUPPORTED;
     }
     // 4w+1 lag rows must stay distinct modulo N (torus wrap of the lag range)
     if (4 * p->w0 + 1 > p->n0 || 4 * p->w1 + 1 > p->n1) return SFFT_E_UNSUPPORTED;
@@ -99,8 +122,14 @@ Geom make_geom(const sfft_params* p) {
 // then the small radices, then the remaining 16s (a radix-16 last pass ends in
 // registers in natural order).
 LinePlan make_line_plan(int n) {
+    if (!direct_length(n)) {   // Bluestein: the plan of its transform length
+        LinePlan lp = make_line_plan(bluestein_length(n));
+        lp.nl = n;
+        return lp;
+    }
     LinePlan lp{};
     lp.n = n;
+    lp.nl = n;
     int a, b;
     radix23(n, &a, &b);
     int np = 0;
@@ -149,6 +178,30 @@ static hipError_t upload(const std::vector<cx<double>>& v, void** dst) {
     return hipMemcpy(*dst, h.data(), h.size() * sizeof(cx<T>), hipMemcpyHostToDevice);
 }
 
+// In-place forward DFT (e^-) of a power-of-two length, iterative radix 2,
+// in long double (the Bluestein tables).
+static void fft_ld(std::vector<std::complex<long double>>& a) {
+    const size_t m = a.size();
+    for (size_t i = 1, j = 0; i < m; ++i) {
+        size_t bit = m >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (size_t len = 2; len <= m; len <<= 1) {
+        for (size_t k = 0; k < len / 2; ++k) {
+            const long double ang = -two_pi * (long double)k / (long double)len;
+            const std::complex<long double> w(cosl(ang), sinl(ang));
+            for (size_t i = 0; i < m; i += len) {
+                const std::complex<long double> u = a[i + k], v = a[i + k + len / 2] * w;
+                a[i + k] = u + v;
+                a[i + k + len / 2] = u - v;
+            }
+        }
+    }
+}
+
 // Twiddles of length n: the full table W_n^t = e^(-2 pi i t / n), the pass
 // tables of the line plan (pass p: row k holds W_(ns R)^(r k), r < R, in 16
 // entries, ns = product of the earlier radices), and the FP64 cos / sin
@@ -182,10 +235,34 @@ static hipError_t make_twiddles(int n, bool mixed, Twiddles& t) {
     }
     e = hipMalloc(&t.twp, 2 * n * sizeof(double));
     if (e) return e;
-    return hipMemcpy(t.twp, vp.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice);
+    e = hipMemcpy(t.twp, vp.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice);
+    if (e || lp.nl == lp.n) return e;
+    // Bluestein tables: chirp c_t = e^(+i pi t^2 / n) (the exponent reduced
+    // mod 2n), b_t = b_(m-t) = c_t, bhat = DFT_m(b) / m by a radix-2 FFT in
+    // long double
+    const int m = lp.n;
+    std::vector<cx<double>> chirp(n);
+    std::vector<std::complex<long double>> b(m, {0.0L, 0.0L});
+    for (int k = 0; k < n; ++k) {
+        const long long q = ((long long)k * k) % (2LL * n);
+        const long double ang = two_pi * 0.5L * (long double)q / (long double)n;
+        const std::complex<long double> c(cosl(ang), sinl(ang));
+        chirp[k] = {(double)c.real(), (double)c.imag()};
+        b[k] = c;
+        if (k > 0) b[m - k] = c;
+    }
+    fft_ld(b);
+    std::vector<cx<double>> bh(m);
+    for (int k = 0; k < m; ++k) bh[k] = {(double)(b[k].real() / m), (double)(b[k].imag() / m)};
+    e = upload<double>(chirp, &t.chirp);   // FP64 in both forms
+    if (e) return e;
+    return upload<double>(bh, &t.bhat);
 }
 
 static void free_twiddles(Twiddles& t) {
+    if (t.chirp) (void)hipFree(t.chirp);
+    if (t.bhat) (void)hipFree(t.bhat);
+    t.chirp = t.bhat = nullptr;
     if (t.tw) (void)hipFree(t.tw);
     if (t.twt) (void)hipFree(t.twt);
     t.twt = nullptr;
@@ -243,6 +320,10 @@ int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out,
     rc = get_twiddles(ctx, p->n0, mixed, &pl->t0);
     if (!rc) rc = get_twiddles(ctx, p->n1, mixed, &pl->t1);
     if (rc) return rc;
+    pl->lp0.chirp = pl->t0.chirp;
+    pl->lp0.bhat = pl->t0.bhat;
+    pl->lp1.chirp = pl->t1.chirp;
+    pl->lp1.bhat = pl->t1.bhat;
     char* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess) return SFFT_E_NOMEM;
     carve(pl->ws, pl->g, mixed ? 8 : 16, mixed ? 4 : 8, base);
@@ -450,7 +531,11 @@ static hipError_t factor_solve(Plan& pl, const double* G, const double* h, doubl
 
 // One refinement step: gradient Phi^T (S_fit - Phi coef) of the current
 // difference image of the fit pair (Z, X, ped hold the fit pair's
-// transforms), correction solved with the existing factor.
+// transforms), correction solved with the existing factor. Every component
+// comes from that one difference image: the rounding of its FP32 evaluation
+// then enters the gradient as Phi^T e, whose least-squares image G^-1 Phi^T e
+// is the fit of e itself (small); taking some components exactly and the
+// others from D breaks that consistency, and G^-1 amplifies the mismatch.
 template <typename T>
 static hipError_t refine(Plan& pl, double* coef, int gen, hipStream_t st) {
     const Geom& g = pl.g;
@@ -970,8 +1055,8 @@ int sfft_lag_tables(sfft_ctx* ctx, const sfft_params* p, const void* r_fit, cons
 int sfft_fft_lines(sfft_ctx* ctx, int n, int lines, int sign, int dtype, const void* in, void* out,
                    void* stream) {
     if (!ctx || !in || !out || lines < 0 || (sign != 1 && sign != -1)) return SFFT_E_INVAL;
-    int a, b;
-    if (n < 16 || n % 16 || n > 8192 || !radix23(n, &a, &b)) return SFFT_E_UNSUPPORTED;
+    if (n < 2 || (direct_length(n) ? n > kMaxLine : bluestein_length(n) > kMaxLine))
+        return SFFT_E_UNSUPPORTED;
     if (dtype != SFFT_F32 && dtype != SFFT_F64) return SFFT_E_INVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
     (void)hipSetDevice(ctx->device);
@@ -979,6 +1064,8 @@ int sfft_fft_lines(sfft_ctx* ctx, int n, int lines, int sign, int dtype, const v
     int rc = get_twiddles(ctx, n, dtype == SFFT_F32, &t);
     if (rc) return rc;
     LinePlan lp = make_line_plan(n);
+    lp.chirp = t.chirp;
+    lp.bhat = t.bhat;
     hipError_t e;
     if (dtype == SFFT_F32)
         e = launch_fft_lines<float>(lp, lines, sign, (const cx<float>*)in, (cx<float>*)out,

@@ -101,8 +101,11 @@ constexpr int kMaxDegree = 4;   // largest DK and DB
 // Elements of one line held by one thread during a transform.
 constexpr int kElemsPerThread = 16;
 
-// Plan of one line length N = 2^a 3^b (multiple of 16): radix sequence and
-// the thread layout (TL threads per line, LPW lines per workgroup).
+// Plan of one line of nl points: the transform length n (nl itself when
+// nl = 2^a 3^b is a multiple of 16; otherwise the Bluestein length, the
+// power of two >= 2 nl - 1), its radix sequence and the thread layout (TL
+// threads per line, LPW lines per workgroup). Element t of the line sits in
+// register e of thread lt = t mod TL, e = t / TL; t >= nl is padding.
 struct LinePlan {
     int n;
     int npass;
@@ -110,6 +113,12 @@ struct LinePlan {
     int twoff[kMaxPass];   // offset of pass p's twiddle table (pass tables)
     int tl;     // threads per line = n / kElemsPerThread
     int lpw;    // lines per workgroup
+    int nl;     // points of the line
+    // Bluestein (chirp-z) lines, null otherwise: chirp[t] = e^(+i pi t^2 / nl)
+    // (t < nl) and bhat = DFT_n(b) / n with b_t = b_(n-t) = chirp[t], both
+    // cx<double>.
+    const void* chirp;
+    const void* bhat;
 };
 
 // Geometry of one subtraction problem (Eq. 1-6): image N0 x N1 (x = axis 0),

@@ -293,6 +293,48 @@ __device__ __forceinline__ void line_fft(cx<T>* v, cx<T>* buf, const LinePlan& l
     }
 }
 
+// The DFT of a line of lp.nl points, in the layout of line_fft (element t in
+// register t / TL of thread t mod TL; entries t >= nl are ignored on input
+// and zero on output). With lp.nl = lp.n this is line_fft; otherwise the
+// Bluestein form of the forward DFT,
+//   X_k = conj(c_k) sum_t (x_t conj(c_t)) c_(k-t),  c_t = e^(+i pi t^2 / nl),
+// the sum a circular convolution of length n >= 2 nl - 1 evaluated as
+// IDFT_n(DFT_n(a) DFT_n(b)) / n (the 1/n is in bhat); the inverse (S = +1)
+// is conj(forward(conj(x))).
+template <int S, typename T, typename PL>
+__device__ __forceinline__ void line_dft(cx<T>* v, cx<T>* buf, const LinePlan& lp, int lt,
+                                         const cx<T>* __restrict__ twt) {
+    if (!lp.chirp) {
+        line_fft<S, T, PL>(v, buf, lp, lt, twt);
+        return;
+    }
+    // the tables are FP64 and every product is formed in FP64 and rounded
+    // once to T (FP64 and FP32 vector rates are equal on this hardware)
+    const cx<double>* __restrict__ ch = static_cast<const cx<double>*>(lp.chirp);
+    const cx<double>* __restrict__ bh = static_cast<const cx<double>*>(lp.bhat);
+    auto wide = [](cx<T> a) { return mk((double)a.re, (double)a.im); };
+    auto narrow = [](cx<double> a) { return mk(T(a.re), T(a.im)); };
+#pragma unroll
+    for (int e = 0; e < kElemsPerThread; ++e) {
+        const int t = lt + e * lp.tl;
+        const bool in = t < lp.nl;
+        const cx<double> c = ch[in ? t : 0];
+        const cx<T> x = S > 0 ? cconj(v[e]) : v[e];
+        v[e] = in ? narrow(cmulc(c, wide(x))) : mk(T(0), T(0));
+    }
+    line_fft<-1, T, PL>(v, buf, lp, lt, twt);
+#pragma unroll
+    for (int e = 0; e < kElemsPerThread; ++e) v[e] = narrow(cmul(wide(v[e]), bh[lt + e * lp.tl]));
+    line_fft<1, T, PL>(v, buf, lp, lt, twt);
+#pragma unroll
+    for (int e = 0; e < kElemsPerThread; ++e) {
+        const int t = lt + e * lp.tl;
+        const bool in = t < lp.nl;
+        const cx<T> y = narrow(cmulc(ch[in ? t : 0], wide(v[e])));
+        v[e] = in ? (S > 0 ? cconj(y) : y) : mk(T(0), T(0));
+    }
+}
+
 // Calls f(PL{}) with the compile-time plan of length n, or DynPlan.
 template <typename F>
 inline hipError_t with_line_plan(int n, F&& f) {

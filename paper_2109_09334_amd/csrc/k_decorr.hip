@@ -103,27 +103,38 @@ __global__ void __launch_bounds__(512) colconv_kernel(Geom g, LinePlan lp, cx<T>
     cx<T>* zc = Z + m;
     cx<T> v[kElemsPerThread];
 #pragma unroll
-    for (int e = 0; e < kElemsPerThread; ++e)
-        v[e] = act ? zc[(size_t)(lt + e * lp.tl) * g.hp] : mk(T(0), T(0));
-    line_fft<-1, T, PL>(v, buf, lp, lt, twt);
+    for (int e = 0; e < kElemsPerThread; ++e)   // rows >= n0: a Bluestein line's padding
+        v[e] = act && lt + e * lp.tl < n0 ? zc[(size_t)(lt + e * lp.tl) * g.hp] : mk(T(0), T(0));
+    line_dft<-1, T, PL>(v, buf, lp, lt, twt);
+    // the column's stamp row DFTs k_(s,a)(m) staged in the line's LDS buffer,
+    // free between the two transforms (read from HBM where a short line's
+    // buffer cannot hold them)
+    const int nst = 1 + M + N, nk = nst * g.L0;
+    const bool staged = nk <= line_lds_elems(lp.n);
+    __syncthreads();
+    if (act && staged)
+        for (int i = lt; i < nk; i += lp.tl) buf[i] = kr[(size_t)i * g.hp + m];
+    __syncthreads();
+    const cx<T>* kb = staged ? buf : kr + m;
+    const size_t kst = staged ? 1 : (size_t)g.hp;
     if (act) {
         const T den0 = T(wts[0]);
         const T inv_n0 = T(1) / T(n0);
-        const int nst = 1 + M + N;
 #pragma unroll 1
         for (int e = 0; e < kElemsPerThread; ++e) {
             const int l = lt + e * lp.tl;
+            if (l >= n0) continue;
+            const cx<T> t1 = tw[l];   // W^l; W^(l a) by the recurrence t <- t W^l
             T gsum = T(0), hsum = T(0), kk = T(0);
 #pragma unroll 1
             for (int s = 0; s < nst; ++s) {
                 // stamp spectrum at (l, m): k_0 + sum_a W^(l a) k_a + conj(W^(l a)) k_-a
-                const cx<T>* ka = kr + ((size_t)s * g.L0 + w0) * g.hp + m;
-                cx<T> acc = ka[0];
-#pragma unroll 1
+                const cx<T>* ka = kb + (size_t)(s * g.L0 + w0) * kst;
+                cx<T> acc = ka[0], t = t1;
+#pragma unroll 4
                 for (int a = 1; a <= w0; ++a) {
-                    const cx<T> t = tw[(size_t)(((long long)l * a) % n0)];
-                    const cx<T> kp = ka[(size_t)a * g.hp], km = ka[-(ptrdiff_t)a * g.hp];
-                    acc = acc + cmul(t, kp) + cmul(cconj(t), km);
+                    acc = acc + cmul(t, ka[(size_t)a * kst]) + cmul(cconj(t), ka[-(ptrdiff_t)a * (ptrdiff_t)kst]);
+                    t = cmul(t, t1);
                 }
                 const T p2 = acc.re * acc.re + acc.im * acc.im;
                 if (s == 0)
@@ -138,10 +149,11 @@ __global__ void __launch_bounds__(512) colconv_kernel(Geom g, LinePlan lp, cx<T>
             v[e] = cscale(v[e], q);
         }
     }
-    line_fft<1, T, PL>(v, buf, lp, lt, twt);
+    line_dft<1, T, PL>(v, buf, lp, lt, twt);
     if (act) {
 #pragma unroll
-        for (int e = 0; e < kElemsPerThread; ++e) zc[(size_t)(lt + e * lp.tl) * g.hp] = v[e];
+        for (int e = 0; e < kElemsPerThread; ++e)
+            if (lt + e * lp.tl < n0) zc[(size_t)(lt + e * lp.tl) * g.hp] = v[e];
     }
 }
 

@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
     const int xa = src.rowpair ? 2 * row : row, xb = src.rowpair ? 2 * row + 1 : row;
     const bool act = xb < g.n0;
     const int n1 = g.n1;
-    cx<T>* buf = lds + line * line_lds_elems(n1);
+    cx<T>* buf = lds + line * line_lds_elems(lp.n);
     const int npk = (src.n + 1) / 2;
 #pragma unroll 1
     for (int pk = 0; pk < npk; ++pk) {
@@ -55,24 +55,27 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
             const double qb = hasb && src.ped[ib] >= 0 ? ped[src.ped[ib]] : 0.0;
             // both rows loaded unconditionally (pb is a valid row when the
             // pair has no second source), then the weights applied
+            // (a Bluestein line's padding, t >= n1, loads a valid pixel and
+            // is zeroed after)
             Tin la[kElemsPerThread], lb[kElemsPerThread];
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e) {
-                la[e] = pa[lt + e * lp.tl];
-                lb[e] = pb[lt + e * lp.tl];
+                const int t = min(lt + e * lp.tl, n1 - 1);
+                la[e] = pa[t];
+                lb[e] = pb[t];
             }
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e) {
                 const T c = coord<T>(lt + e * lp.tl, n1);
                 const T va = ipow_upto<kMaxDegree>(c, ea) * T((double)la[e] - qa);
                 const T vb = hasb ? ipow_upto<kMaxDegree>(c, eb) * T((double)lb[e] - qb) : T(0);
-                v[e] = mk(va, vb);
+                v[e] = lt + e * lp.tl < n1 ? mk(va, vb) : mk(T(0), T(0));
             }
         } else {
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e) v[e] = mk(T(0), T(0));
         }
-        line_fft<-1, T, PL>(v, buf, lp, lt, twt);
+        line_dft<-1, T, PL>(v, buf, lp, lt, twt);
         // separate the two real rows: needs X(m) and X(N1 - m) together
         __syncthreads();
 #pragma unroll
@@ -122,7 +125,8 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
     if constexpr (kHold) {
         if (act) {
 #pragma unroll
-            for (int e = 0; e < kElemsPerThread; ++e) z[e] = zc[(size_t)(lt + e * lp.tl) * g.hp];
+            for (int e = 0; e < kElemsPerThread; ++e)
+                z[e] = zc[(size_t)min(lt + e * lp.tl, n0 - 1) * g.hp];
         }
     }
     const int nw = jobs.nw[job];
@@ -141,18 +145,21 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
                 for (int e = 0; e < kElemsPerThread; ++e) z[e] = cscale(z[e], c0[e]);
             }
 #pragma unroll
-            for (int e = 0; e < kElemsPerThread; ++e) v[e] = act ? z[e] : mk(T(0), T(0));
+            for (int e = 0; e < kElemsPerThread; ++e)
+                v[e] = act && lt + e * lp.tl < n0 ? z[e] : mk(T(0), T(0));
         } else {
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e)
-                v[e] = act ? cscale(zc[(size_t)(li + e * lp.tl) * g.hp], ipow(c0[e], i))
+                v[e] = act && li + e * lp.tl < n0
+                           ? cscale(zc[(size_t)min(li + e * lp.tl, n0 - 1) * g.hp], ipow(c0[e], i))
                            : mk(T(0), T(0));
         }
-        line_fft<-1, T, PL>(v, buf, lp, li, twt);
+        line_dft<-1, T, PL>(v, buf, lp, li, twt);
         if (act) {
             cx<T>* xo = X + ((size_t)jobs.spec[job][i] * g.h + m) * n0;
 #pragma unroll
-            for (int e = 0; e < kElemsPerThread; ++e) xo[li + e * lp.tl] = v[e];
+            for (int e = 0; e < kElemsPerThread; ++e)
+                if (li + e * lp.tl < n0) xo[li + e * lp.tl] = v[e];
         }
     }
 }
@@ -185,18 +192,18 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
         // every load is issued unconditionally from the folded index
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) {
-            const int m = lt + e * lp.tl;
-            const int mf = m < g.h ? m : n1 - m;
+            const int m = lt + e * lp.tl;   // >= n1: a Bluestein line's padding
+            const int mf = m < g.h ? m : (m < n1 ? n1 - m : 0);
             cx<T> a = A[mf], b = B[mf];
             if (m >= g.h) { a.im = -a.im; b.im = -b.im; }
             if (m == 0 || 2 * m == n1) { a.im = T(0); b.im = T(0); }
-            v[e] = mk(a.re - b.im, a.im + b.re);
+            v[e] = m < n1 ? mk(a.re - b.im, a.im + b.re) : mk(T(0), T(0));
         }
     } else {
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) v[e] = mk(T(0), T(0));
     }
-    line_fft<1, T, PL>(v, buf, lp, lt, twt);
+    line_dft<1, T, PL>(v, buf, lp, lt, twt);
     if (act) {
         const double inv = 1.0 / (double)n1;
         const int n0 = g.n0, w0 = g.w0, R = max(g.dk, g.db);
@@ -223,7 +230,8 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
             for (int r = 0; r < nsky; ++r) {
                 double y[kChunk];
 #pragma unroll
-                for (int q = 0; q < kChunk; ++q) y[q] = sky[(size_t)r * n1 + lt + (e0 + q) * lp.tl];
+                for (int q = 0; q < kChunk; ++q)
+                    y[q] = sky[(size_t)r * n1 + min(lt + (e0 + q) * lp.tl, n1 - 1)];
 #pragma unroll
                 for (int q = 0; q < kChunk; ++q) {
                     ba[q] += pa * y[q];
@@ -234,15 +242,17 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
             }
             if (ra)
 #pragma unroll
-                for (int q = 0; q < kChunk; ++q) ba[q] = ra[lt + (e0 + q) * lp.tl];
+                for (int q = 0; q < kChunk; ++q) ba[q] = ra[min(lt + (e0 + q) * lp.tl, n1 - 1)];
             if (rb)
 #pragma unroll
-                for (int q = 0; q < kChunk; ++q) bb[q] = rb[lt + (e0 + q) * lp.tl];
+                for (int q = 0; q < kChunk; ++q) bb[q] = rb[min(lt + (e0 + q) * lp.tl, n1 - 1)];
 #pragma unroll
             for (int q = 0; q < kChunk; ++q) {
                 const int x1 = lt + (e0 + q) * lp.tl;
-                d[(size_t)xa * n1 + x1] = Tout((double)v[e0 + q].re * inv - ba[q]);
-                d[(size_t)xb * n1 + x1] = Tout((double)v[e0 + q].im * inv - bb[q]);
+                if (x1 < n1) {
+                    d[(size_t)xa * n1 + x1] = Tout((double)v[e0 + q].re * inv - ba[q]);
+                    d[(size_t)xb * n1 + x1] = Tout((double)v[e0 + q].im * inv - bb[q]);
+                }
             }
         }
     }
@@ -258,14 +268,16 @@ __global__ void __launch_bounds__(512) fft_lines_kernel(LinePlan lp, int nlines,
     const int ln = blockIdx.x * lp.lpw + line;
     const bool act = ln < nlines;
     cx<T>* buf = lds + line * line_lds_elems(lp.n);
+    const int nl = lp.nl;   // the lines' points (lp.n: the transform length)
     cx<T> v[kElemsPerThread];
 #pragma unroll
     for (int e = 0; e < kElemsPerThread; ++e)
-        v[e] = act ? in[(size_t)ln * lp.n + lt + e * lp.tl] : mk(T(0), T(0));
-    line_fft<S, T, PL>(v, buf, lp, lt, twt);
+        v[e] = act && lt + e * lp.tl < nl ? in[(size_t)ln * nl + lt + e * lp.tl] : mk(T(0), T(0));
+    line_dft<S, T, PL>(v, buf, lp, lt, twt);
     if (act)
 #pragma unroll
-        for (int e = 0; e < kElemsPerThread; ++e) out[(size_t)ln * lp.n + lt + e * lp.tl] = v[e];
+        for (int e = 0; e < kElemsPerThread; ++e)
+            if (lt + e * lp.tl < nl) out[(size_t)ln * nl + lt + e * lp.tl] = v[e];
 }
 
 // ---------------------------------------------------------------- launchers

@@ -66,20 +66,21 @@ __global__ void __launch_bounds__(512) lagcol_kernel(Geom g, LinePlan lp, int p0
         const cx<T>* B = X + ((size_t)k * g.h + m) * n0;
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) {
-            const int l = lt + e * lp.tl;
-            v[e] = cmulc(A[l], B[l]);
+            const int l = lt + e * lp.tl;   // >= n0: a Bluestein line's padding
+            const int lc = min(l, n0 - 1);
+            v[e] = l < n0 ? cmulc(A[lc], B[lc]) : mk(T(0), T(0));
         }
     } else {
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) v[e] = mk(T(0), T(0));
     }
-    line_fft<1, T, PL>(v, buf, lp, lt, twt);
+    line_dft<1, T, PL>(v, buf, lp, lt, twt);
     if (act) {
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) {
             const int l = lt + e * lp.tl;   // lag d0 = l or l - N0
             const int d0 = l <= K ? l : l - n0;
-            if (d0 >= -K && d0 <= K)
+            if (l < n0 && d0 >= -K && d0 <= K)
                 Cl[((size_t)p * g.D0 + d0 + 2 * g.w0) * g.hp + m] = v[e];
         }
     }
@@ -448,7 +449,8 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
                          hipStream_t st) {
     if (p1 <= p0) return hipSuccess;
     static const bool force_full = getenv("SFFT_LAGCOL_FULL") != nullptr;
-    if (!force_full && lp.tl % 64 == 0 && lp.tl * lp.lpw <= 512 &&
+    // (the pruned pass needs N0 = 16 x its threads per line: not a Bluestein line)
+    if (!force_full && !lp.chirp && lp.tl % 64 == 0 && lp.tl * lp.lpw <= 512 &&
         ((p0 == 0 && p1 == g.nprod) || (p0 == g.npair && p1 == g.nprod))) {
         const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
         const int nwv = lp.tl * lp.lpw / 64;

@@ -127,6 +127,8 @@ int run_noalloc(int device, const sfft_params* p, const void* rf, const void* sf
     pl.g = make_geom(p);
     pl.lp0 = make_line_plan(p->n0);
     pl.lp1 = make_line_plan(p->n1);
+    // lengths that need Bluestein tables (formed on the host) are not served here
+    if (pl.lp0.nl != pl.lp0.n || pl.lp1.nl != pl.lp1.n) return SFFT_E_UNSUPPORTED;
     pl.device = device;
     if (carve_all(pl, nullptr) > kScratchBytes) return SFFT_E_NOMEM;
     carve_all(pl, base);

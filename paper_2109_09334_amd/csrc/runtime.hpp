@@ -104,6 +104,8 @@ struct Twiddles {
     void* tw = nullptr;       // n complex of the compute type: e^(-2 pi i t / n)
     void* twt = nullptr;      // pass tables of the line plan (compute type)
     double* twp = nullptr;    // 2n doubles: cos, sin of +2 pi t / n
+    void* chirp = nullptr;    // Bluestein lines: the plan's chirp and bhat
+    void* bhat = nullptr;     // tables (cx<double>), null otherwise
 };
 
 // Per-stage HIP-event timers (enabled by sfft_profile): every stage of the

@@ -54,11 +54,24 @@ def test_library_loads_and_host_logic():
     assert ok(P(4096, 4096, 7, 7, 2, 2)) == sf.OK
     assert ok(P(6144, 6144, 7, 7, 2, 2)) == sf.OK
     assert ok(P(2048, 4096, 5, 5, 1, 1)) == sf.OK
-    assert ok(P(100, 128, 3, 3, 1, 1)) == sf.E_UNSUPPORTED     # 100 = 4 * 25
-    assert ok(P(80, 64, 3, 3, 1, 1)) == sf.E_UNSUPPORTED       # radix 5
+    # lengths other than 2^a 3^b run as Bluestein lines of a power of two <= 8192
+    assert ok(P(100, 128, 3, 3, 1, 1)) == sf.OK                # 100 = 4 * 25
+    assert ok(P(2046, 4094, 7, 7, 2, 2)) == sf.OK              # DECam CCD: 2 3 11 31, 2 23 89
+    assert ok(P(4096, 4098, 7, 7, 2, 2)) == sf.E_UNSUPPORTED   # its Bluestein length 16384
+    assert ok(P(101, 128, 3, 3, 1, 1)) == sf.E_UNSUPPORTED     # odd
+    assert ok(P(8192, 8192, 3, 3, 1, 1)) == sf.OK
     assert ok(P(64, 64, -1, 3, 1, 1)) == sf.E_INVAL
     assert ok(P(64, 64, 3, 3, 1, 1, precision=7)) == sf.E_INVAL
     assert ok(P(16, 16, 8, 8, 0, 0)) == sf.E_INVAL             # 2w+1 > n
     assert ok(P(64, 64, 3, 3, 5, 1)) == sf.E_UNSUPPORTED       # DK > 4
+    # the mixed form: FP32 images, DK <= 3, sides of 48 pixels or more
+    M = dict(precision=sf.MIXED)
+    assert ok(P(64, 64, 3, 3, 3, 1, **M)) == sf.OK
+    assert ok(P(64, 64, 3, 3, 4, 1, **M)) == sf.E_UNSUPPORTED
+    assert ok(P(64, 64, 3, 3, 1, 1, dtype=sf.F64, **M)) == sf.E_UNSUPPORTED
+    assert ok(P(2046, 48, 9, 2, 1, 1, **M)) == sf.OK
+    assert ok(P(2046, 34, 9, 2, 1, 1, **M)) == sf.E_UNSUPPORTED
+    assert ok(P(32, 8192, 3, 2, 1, 1, **M)) == sf.E_UNSUPPORTED
+    assert ok(P(32, 8192, 3, 2, 1, 1, precision=sf.FP64)) == sf.OK
     assert sf.Context.workspace_bytes(P(4096, 4096, 7, 7, 2, 2)) > 0
     assert L.sfft_strerror(sf.E_NOT_SPD).decode().startswith("normal matrix")

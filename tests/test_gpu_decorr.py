@@ -86,7 +86,9 @@ CASES = [
     (96, 48, 3, 2, 2, 0, 2, 3, 0.3, -0.7),
     (48, 64, 1, 4, 1, 1, 1, 1, -1.0, 1.0),
     (144, 96, 6, 5, 3, 0, 8, 8, 0.9, 0.1),
-    (2048, 32, 16, 2, 0, 0, 3, 1, 0.0, 0.5),
+    (2048, 48, 16, 2, 0, 0, 3, 1, 0.0, 0.5),
+    (32, 2048, 2, 7, 1, 0, 1, 1, 0.5, 0.0),   # (mixed form refused: 32 rows)
+    (94, 110, 3, 4, 1, 0, 1, 2, 0.2, 0.2),    # Bluestein lines (2 47, 2 5 11)
 ]
 
 
@@ -107,6 +109,11 @@ def test_decorrelate_coadds(sfft, ctx, case, prec, dtype):
     ss, sr = rng.uniform(5, 15, M), rng.uniform(5, 15, N)
     p = sfft.Params(n0, n1, w0, w1, dk, 0, cp, sfft.FP64 if prec == "fp64" else sfft.MIXED,
                     sfft.F32 if dtype == "f32" else sfft.F64)
+    if prec == "mixed" and min(n0, n1) < 48:   # strips the mixed form refuses
+        with pytest.raises(sfft.SfftError) as ei:
+            _run(sfft, ctx, p, coef, d, u0, u1, ss, sr, g, h)
+        assert ei.value.code == sfft.E_UNSUPPORTED
+        return
     got = _run(sfft, ctx, p, coef, d, u0, u1, ss, sr, g, h)
     ref = _expect(p, coef, d.astype(np.float64), u0, u1, ss, sr, g, h)
     _check(f"{case} {prec} {dtype}", sfft, p, got, ref)

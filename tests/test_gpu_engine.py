@@ -296,3 +296,26 @@ def test_direct_batch_reports_a_bad_pair(sfft):
         for k in (0, 2, 3):
             assert torch.equal(items[k][4], refs[k])
         ctx.sync()   # reported once
+
+
+def test_batch_of_bluestein_pairs_equals_alone(sfft):
+    """A batch of pairs whose lengths need Bluestein lines (94 x 110) through
+    the engine: each equals its direct call bit for bit."""
+    n0, n1, w, dk, db = 94, 110, 3, 2, 2
+    p = sfft.Params(n0, n1, w, w, dk, db, 0, sfft.MIXED, sfft.F32)
+    with sfft.Context(0) as eager, sfft.Context(0) as ctx:
+        ctx.engine_config(1, 4)
+        refs, jobs = [], []
+        for k in range(4):
+            R, S = _inputs(950 + k, n0, n1, w, dk, db)
+            c, d = eager.run(p, R, S)
+            eager.sync()
+            refs.append((c.clone(), d.clone()))
+            co = torch.empty(p.num_unknowns, dtype=torch.float64, device="cuda")
+            do = torch.empty((n0, n1), dtype=torch.float32, device="cuda")
+            jobs.append((ctx.submit(p, R, S, R, S, co, do), co, do))
+        for k, (t, co, do) in enumerate(jobs):
+            assert ctx.wait(t) == sfft.OK
+        torch.cuda.synchronize()
+        for k, (t, co, do) in enumerate(jobs):
+            assert torch.equal(co, refs[k][0]) and torch.equal(do, refs[k][1]), k

@@ -29,7 +29,8 @@ CASES = [
     # tall images: column transforms with 64, 128 and 192 threads per line
     (1024, 64, 3, 3, 2, 2, 0),
     (2048, 48, 2, 2, 1, 1, 1),
-    (3072, 32, 2, 2, 2, 1, 0),
+    (3072, 48, 2, 2, 2, 1, 0),
+    (3072, 32, 2, 2, 2, 1, 0),    # (mixed form refused: 32 columns)
     # the rest of the parameter space the library accepts:
     # w0 != w1 (Eq. 3-4 allow independent half widths), DB > DK
     (64, 96, 2, 4, 1, 2, 0),
@@ -43,9 +44,16 @@ CASES = [
     (1024, 48, 9, 2, 1, 1, 0),
     (2048, 64, 16, 8, 0, 0, 0),
     # largest and smallest line lengths
-    (8192, 32, 2, 2, 1, 0, 0),
-    (32, 8192, 3, 2, 1, 1, 0),
+    (8192, 48, 2, 2, 1, 0, 0),
+    (48, 8192, 3, 2, 1, 1, 0),
     (16, 16, 1, 3, 0, 0, 0),
+    # lengths with factors other than 2 and 3 (Bluestein lines): 46 = 2 23,
+    # 62 = 2 31, 94 = 2 47, 50 = 2 5^2, 110 = 2 5 11, 2046 = 2 3 11 31
+    (46, 62, 2, 2, 1, 1, 0),
+    (94, 50, 3, 3, 2, 2, 0),
+    (110, 96, 4, 2, 2, 1, 1),
+    (2046, 34, 9, 2, 1, 1, 0),    # (mixed form refused: 34 columns)
+    (2046, 62, 9, 2, 1, 1, 0),
 ]
 
 
@@ -75,9 +83,10 @@ def _params(sfft, n0, n1, w0, w1, dk, db, cp, prec, dtype):
     return sfft.Params(n0, n1, w0, w1, dk, db, cp, prec, dtype)
 
 
-def _mixed_refused(sfft, prec, dtype, dk):
-    """The parameter sets the mixed form refuses (FP64 images, DK = 4)."""
-    return prec == "mixed" and (dtype == "f64" or dk > 3)
+def _mixed_refused(sfft, prec, dtype, dk, n0=64, n1=64):
+    """The parameter sets the mixed form refuses (FP64 images, DK = 4, a side
+    under 48 pixels)."""
+    return prec == "mixed" and (dtype == "f64" or dk > 3 or min(n0, n1) < 48)
 
 
 def _assert_refused(sfft, ctx, p, R, S):
@@ -87,7 +96,9 @@ def _assert_refused(sfft, ctx, p, R, S):
     assert ei.value.code == sfft.E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("n", [16, 48, 96, 256, 384, 1024, 4096, 6144, 8192])
+@pytest.mark.parametrize("n", [16, 48, 96, 256, 384, 1024, 4096, 6144, 8192,
+                               # Bluestein lines (lengths with factors other than 2, 3)
+                               18, 46, 62, 100, 1000, 2046, 4094, 4095])
 @pytest.mark.parametrize("cdt", [torch.complex128, torch.complex64])
 def test_fft_lines_vs_numpy(ctx, n, cdt):
     rng = np.random.default_rng(n)
@@ -116,7 +127,7 @@ def test_lag_tables_and_system(sfft, ctx, case, prec):
         s = s.astype(np.float32).astype(np.float64)
     tdt = torch.float64 if prec == "fp64" else torch.float32
     p = _params(sfft, n0, n1, w0, w1, dk, db, cp, pr, dt)
-    if _mixed_refused(sfft, prec, "f32", dk):
+    if _mixed_refused(sfft, prec, "f32", dk, n0, n1):
         _assert_refused(sfft, ctx, p, _dev(r, tdt), _dev(s, tdt))
         return
     tab = ctx.lag_tables(p, _dev(r, tdt), _dev(s, tdt))
@@ -156,7 +167,7 @@ def test_run_matches_oracle(sfft, ctx, case, prec, dtype):
     tdt = torch.float32 if dtype == "f32" else torch.float64
     pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
     p = _params(sfft, n0, n1, w0, w1, dk, db, cp, pr, sfft.F32 if dtype == "f32" else sfft.F64)
-    if _mixed_refused(sfft, prec, dtype, dk):
+    if _mixed_refused(sfft, prec, dtype, dk, n0, n1):
         _assert_refused(sfft, ctx, p, _dev(r, tdt), _dev(s, tdt))
         return
     coef, d = ctx.run(p, _dev(r, tdt), _dev(s, tdt))
@@ -225,7 +236,7 @@ def test_apply_pair_differs_from_fit_pair(sfft, ctx, case, prec, dtype):
     tdt = torch.float32 if dtype == "f32" else torch.float64
     pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
     p = _params(sfft, n0, n1, w, w, dk, db, 0, pr, sfft.F32 if dtype == "f32" else sfft.F64)
-    if _mixed_refused(sfft, prec, dtype, dk):
+    if _mixed_refused(sfft, prec, dtype, dk, n0, n1):
         _assert_refused(sfft, ctx, p, _dev(r, tdt), _dev(s, tdt))
         return
     coef, d = ctx.run(p, _dev(rm, tdt), _dev(sm, tdt), _dev(r, tdt), _dev(s, tdt))

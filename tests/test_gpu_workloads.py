@@ -185,3 +185,16 @@ def test_config4_sizes_served_vs_oracle(sfft, shape):
     else:
         co = oracle.fit(pair.r.astype(np.float64), pair.s.astype(np.float64), 5, 5, 1, 1)
     _check_against_oracle(f"C4 {n0}x{n1} served", pair, out, co, 5, 1, 1)
+
+
+@pytest.mark.timeout(900)
+def test_decam_ccd_shape_served_vs_oracle(sfft):
+    """The paper's DECam CCD shape (Table 2), 2046 x 4094 = (2 3 11 31) x
+    (2 23 89): Bluestein lines along both axes. 17 x 17 kernel (w = 8, about
+    twice the seeing FWHM of the synthetic field), DK = DB = 2, both forms,
+    served, in full against the oracle."""
+    n0, n1, w = 2046, 4094, 8
+    pair = datagen.star_pair(2046, n0, n1, w=w, dk=2, db=2)
+    out = _served(sfft, pair, _forms(sfft, n0, n1, w, 2, 2))
+    co = oracle.fit(pair.r.astype(np.float64), pair.s.astype(np.float64), w, w, 2, 2)
+    _check_against_oracle("DECam 2046x4094 served", pair, out, co, w, 2, 2)
