@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--stars", type=int, default=40000)
     ap.add_argument("--stream-requests", type=int, default=2000,
                     help="requests timed per load point of the serving stream")
+    ap.add_argument("--stream-max-pending", type=int, default=256,
+                    help="requests in flight past which a stream load point counts as overloaded")
     ap.add_argument("--stream-warmup", type=int, default=200,
                     help="untimed requests before them at each load point")
     ap.add_argument("--distinct", type=int, default=16,
@@ -387,14 +389,22 @@ def main():
 
     def mix_stream(prec, rate, count, warm):
         """Poisson arrivals at `rate`; latency = completion - arrival, host
-        clock, queueing included; the first `warm` requests are not counted."""
+        clock, queueing included; the first `warm` requests are not counted.
+        A rate above what the engine sustains grows the queue without bound:
+        past --stream-max-pending requests in flight the arrivals stop, the
+        queue drains and the point is marked overloaded (its percentiles are
+        then those of the requests that were admitted)."""
         rqs = mix_requests(count + warm, seed=7)
         arrivals = datagen.poisson_arrivals(count + warm, rate, seed=7)
-        lat, pending = [], {}
+        lat, pending, failed = [], {}, []
+        overloaded = False
         t_start = time.perf_counter()
         i = 0
         while i < len(rqs) or pending:
             now = time.perf_counter() - t_start
+            if i < len(rqs) and len(pending) > args.stream_max_pending:
+                overloaded = True
+                rqs = rqs[:i]
             while i < len(rqs) and arrivals[i] <= now:
                 rq = rqs[i]
                 p = mix_params(rq, prec)
@@ -404,16 +414,23 @@ def main():
                 pending[tk] = (arrivals[i], i, p, o)
                 i += 1
             for tk in list(pending):
-                if strm.poll(tk) == sf.OK:
-                    arr, k, p, o = pending.pop(tk)
-                    if k >= warm:
-                        lat.append(time.perf_counter() - t_start - arr)
-                    give_out(p, o)
+                st_ = strm.poll(tk)
+                if st_ == sf.PENDING:
+                    continue
+                arr, k, p, o = pending.pop(tk)
+                if st_ != sf.OK:
+                    failed.append(st_)
+                elif k >= warm:
+                    lat.append(time.perf_counter() - t_start - arr)
+                give_out(p, o)
             time.sleep(5e-5)
-        lat = np.array(lat) * 1e3
-        return {"rate_per_s": rate, "requests": count, "warmup_requests": warm,
+        lat = np.array(lat) * 1e3 if lat else np.array([np.nan])
+        if failed:
+            raise RuntimeError(f"stream: {len(failed)} requests failed (status {sorted(set(failed))})")
+        return {"rate_per_s": rate, "requests": max(0, len(rqs) - warm), "warmup_requests": warm,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "served_per_s": (count + warm) / (time.perf_counter() - t_start)}
+                "served_per_s": len(rqs) / (time.perf_counter() - t_start),
+                "overloaded": overloaded}
 
     def c4_batch():
         """C4: 64 ragged pairs (512^2 .. 2048x4096, w = 5, DK = DB = 1) served
@@ -474,6 +491,10 @@ def main():
                 log(f"[bench] {name} stream at {frac:.2f} x {sat:.1f}/s: p50 {pts[str(frac)]['p50_ms']:.2f} "
                     f"ms p99 {pts[str(frac)]['p99_ms']:.2f} ms")
             stream[name] = {"saturated_pairs_per_s": sat, "loads": pts}
+    # the stream's workspaces and output buffers are not needed below
+    strm.close()
+    out_pool.clear()
+    torch.cuda.empty_cache()
     c4 = None if args.no_c4 else c4_batch()
     if c4:
         log(f"[bench] C4 batch: {c4['pairs_per_s']:.1f} pairs/s")

@@ -73,7 +73,7 @@ enum {
     SFFT_OK = 0,
     SFFT_PENDING = 1,          /* sfft_poll: request not finished yet */
     SFFT_E_INVAL = -1,         /* invalid argument or parameter set */
-    SFFT_E_NOMEM = -2,         /* workspace does not fit the HBM budget */
+    SFFT_E_NOMEM = -2,         /* workspace does not fit the HBM budget, or device memory ran out */
     SFFT_E_NOT_SPD = -3,       /* normal matrix not positive definite */
     SFFT_E_NONFINITE = -4,     /* NaN or Inf in the inputs / normal matrix */
     SFFT_E_UNSUPPORTED = -5,   /* odd or too large a size, parameters out of range */

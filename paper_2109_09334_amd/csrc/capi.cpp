@@ -277,7 +277,13 @@ using namespace sfft;
 
 namespace sfft {
 
-static int hip_status(hipError_t e) { return e == hipSuccess ? SFFT_OK : SFFT_E_HIP; }
+// Status of a HIP result: device memory exhausted (e.g. a graph
+// instantiated under memory pressure) is SFFT_E_NOMEM, other failures
+// SFFT_E_HIP.
+static int hip_status(hipError_t e) {
+    if (e == hipSuccess) return SFFT_OK;
+    return e == hipErrorOutOfMemory ? SFFT_E_NOMEM : SFFT_E_HIP;
+}
 
 // Twiddles are shared by every plan of the context with the same length.
 static int get_twiddles(sfft_ctx* ctx, int n, bool mixed, Twiddles* out) {

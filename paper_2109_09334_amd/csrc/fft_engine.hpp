@@ -293,10 +293,37 @@ __device__ __forceinline__ void line_fft(cx<T>* v, cx<T>* buf, const LinePlan& l
     }
 }
 
+// Plan tag of a Bluestein line: the chirp form below around transforms of
+// length lp.n with the plan P. Lines of other plans have no padding (lp.nl =
+// lp.n), and kernels compile their padding clamps and masks only for this
+// tag (pad_index, in_line).
+template <typename P>
+struct Chirp {
+    using plan = P;
+};
+template <typename PL>
+struct IsChirp : std::false_type {};
+template <typename P>
+struct IsChirp<Chirp<P>> : std::true_type {};
+
+// Index t of a line's element, clamped into its n true points (a padded
+// line's loads past n read a valid element, masked after).
+template <typename PL>
+__device__ __forceinline__ int pad_index(int t, int n) {
+    if constexpr (IsChirp<PL>::value) return t < n ? t : n - 1;
+    else return t;
+}
+// Whether index t is one of the line's n true points.
+template <typename PL>
+__device__ __forceinline__ bool in_line(int t, int n) {
+    if constexpr (IsChirp<PL>::value) return t < n;
+    else return true;
+}
+
 // The DFT of a line of lp.nl points, in the layout of line_fft (element t in
 // register t / TL of thread t mod TL; entries t >= nl are ignored on input
-// and zero on output). With lp.nl = lp.n this is line_fft; otherwise the
-// Bluestein form of the forward DFT,
+// and zero on output). For plans other than Chirp this is line_fft; for
+// Chirp<P> the Bluestein form of the forward DFT,
 //   X_k = conj(c_k) sum_t (x_t conj(c_t)) c_(k-t),  c_t = e^(+i pi t^2 / nl),
 // the sum a circular convolution of length n >= 2 nl - 1 evaluated as
 // IDFT_n(DFT_n(a) DFT_n(b)) / n (the 1/n is in bhat); the inverse (S = +1)
@@ -304,41 +331,51 @@ __device__ __forceinline__ void line_fft(cx<T>* v, cx<T>* buf, const LinePlan& l
 template <int S, typename T, typename PL>
 __device__ __forceinline__ void line_dft(cx<T>* v, cx<T>* buf, const LinePlan& lp, int lt,
                                          const cx<T>* __restrict__ twt) {
-    if (!lp.chirp) {
+    if constexpr (!IsChirp<PL>::value) {
         line_fft<S, T, PL>(v, buf, lp, lt, twt);
-        return;
-    }
-    // the tables are FP64 and every product is formed in FP64 and rounded
-    // once to T (FP64 and FP32 vector rates are equal on this hardware)
-    const cx<double>* __restrict__ ch = static_cast<const cx<double>*>(lp.chirp);
-    const cx<double>* __restrict__ bh = static_cast<const cx<double>*>(lp.bhat);
-    auto wide = [](cx<T> a) { return mk((double)a.re, (double)a.im); };
-    auto narrow = [](cx<double> a) { return mk(T(a.re), T(a.im)); };
+    } else {
+        using P = typename PL::plan;
+        // the tables are FP64 and every product is formed in FP64 and rounded
+        // once to T (FP64 and FP32 vector rates are equal on this hardware)
+        const cx<double>* __restrict__ ch = static_cast<const cx<double>*>(lp.chirp);
+        const cx<double>* __restrict__ bh = static_cast<const cx<double>*>(lp.bhat);
+        auto wide = [](cx<T> a) { return mk((double)a.re, (double)a.im); };
+        auto narrow = [](cx<double> a) { return mk(T(a.re), T(a.im)); };
 #pragma unroll
-    for (int e = 0; e < kElemsPerThread; ++e) {
-        const int t = lt + e * lp.tl;
-        const bool in = t < lp.nl;
-        const cx<double> c = ch[in ? t : 0];
-        const cx<T> x = S > 0 ? cconj(v[e]) : v[e];
-        v[e] = in ? narrow(cmulc(c, wide(x))) : mk(T(0), T(0));
-    }
-    line_fft<-1, T, PL>(v, buf, lp, lt, twt);
+        for (int e = 0; e < kElemsPerThread; ++e) {
+            const int t = lt + e * lp.tl;
+            const bool in = t < lp.nl;
+            const cx<double> c = ch[in ? t : 0];
+            const cx<T> x = S > 0 ? cconj(v[e]) : v[e];
+            v[e] = in ? narrow(cmulc(c, wide(x))) : mk(T(0), T(0));
+        }
+        line_fft<-1, T, P>(v, buf, lp, lt, twt);
 #pragma unroll
-    for (int e = 0; e < kElemsPerThread; ++e) v[e] = narrow(cmul(wide(v[e]), bh[lt + e * lp.tl]));
-    line_fft<1, T, PL>(v, buf, lp, lt, twt);
+        for (int e = 0; e < kElemsPerThread; ++e) v[e] = narrow(cmul(wide(v[e]), bh[lt + e * lp.tl]));
+        line_fft<1, T, P>(v, buf, lp, lt, twt);
 #pragma unroll
-    for (int e = 0; e < kElemsPerThread; ++e) {
-        const int t = lt + e * lp.tl;
-        const bool in = t < lp.nl;
-        const cx<T> y = narrow(cmulc(ch[in ? t : 0], wide(v[e])));
-        v[e] = in ? (S > 0 ? cconj(y) : y) : mk(T(0), T(0));
+        for (int e = 0; e < kElemsPerThread; ++e) {
+            const int t = lt + e * lp.tl;
+            const bool in = t < lp.nl;
+            const cx<T> y = narrow(cmulc(ch[in ? t : 0], wide(v[e])));
+            v[e] = in ? (S > 0 ? cconj(y) : y) : mk(T(0), T(0));
+        }
     }
 }
 
-// Calls f(PL{}) with the compile-time plan of length n, or DynPlan.
+// Calls f(PL{}) with the plan of lp: the compile-time plan of its length or
+// DynPlan, wrapped in Chirp for a Bluestein line (compile-time plans for the
+// transform lengths of 2046 and 4094 points, the DECam CCD sides).
 template <typename F>
-inline hipError_t with_line_plan(int n, F&& f) {
-    switch (n) {
+inline hipError_t with_line_plan(const LinePlan& lp, F&& f) {
+    if (lp.chirp) {
+        switch (lp.n) {
+            case 4096: return f(Chirp<RadixSeq<16, 16, 16>>{});
+            case 8192: return f(Chirp<RadixSeq<16, 2, 16, 16>>{});
+            default: return f(Chirp<DynPlan>{});
+        }
+    }
+    switch (lp.n) {
         case 4096: return f(RadixSeq<16, 16, 16>{});
         case 2048: return f(RadixSeq<16, 8, 16>{});
         case 1024: return f(RadixSeq<16, 4, 16>{});

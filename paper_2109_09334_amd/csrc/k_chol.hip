@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__
 }
 
 // Triangular solves as a dataflow over 64-row blocks, one workgroup per
-// block and direction (T = ceil(n/64) blocks):
+// block and direction (T = ceil(n/64) blocks, 2 T workgroups per pair):
 //   forward  y_B = W_B (D b_B - sum_(C < B) L_BC y_C),        workgroup B
 //   backward z_B = W_B^T (y_B - sum_(C > B) (L^T)_BC z_C),     workgroup 2T-1-B
 // then coef_B (+)= D z_B, with W_B, W_B^T the inverted diagonal blocks and
@@ -453,9 +453,14 @@ __global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__
 // poll until the flag reaches gen, then acquire. The flags are cleared at
 // the start of each request (clear_flag_kernel) and every solve of the
 // request has the next generation, so no solve clears them itself.
-// Every wait is on a workgroup of lower index (dispatched earlier), and each
-// poll is bounded: past the bound the block sets kFlagStall and goes on
-// (its result is then NaN).
+// Every workgroup of a pair runs on one XCD: workgroups are dealt to the 8
+// XCDs round robin and each XCD starts its own in order, so workgroup i
+// (XCD i mod 8, j = i / 8 its place there) takes pair (i mod 8) + 8 (j / 2T)
+// and order x = j mod 2T within it: forward block x for x < T, backward
+// block 2T-1-x after. Every block a workgroup waits for is then earlier on
+// the same XCD, already started, whatever else runs on the other XCDs; the
+// flags stay in one L2. Each poll is bounded: past the bound the block sets
+// kFlagStall and goes on (its result is then NaN).
 // Waits (thread 0, at most `spin` polls) until *f reaches gen, then makes
 // the producer's writes visible to the whole workgroup.
 __device__ __forceinline__ void wait_flag(const int* f, int gen, int spin, int* flag) {
@@ -480,19 +485,26 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
                                                          double* __restrict__ coef, int accumulate,
                                                          int* flag, double* tsv, int* tflag,
                                                          int gen, int wait_gen, int spin,
-                                                         long long zstride) {
+                                                         int npairs, long long zstride) {
     __shared__ double vsh[NBK];
-    L = zoff(L, zstride);
-    dinv = zoff(dinv, zstride);
-    dsc = zoff(dsc, zstride);
-    b = zoff(b, zstride);
-    coef = zoff(coef, zstride);
-    flag = zoff(flag, zstride);
-    tsv = zoff(tsv, zstride);
-    tflag = zoff(tflag, zstride);
     const int T = (n + NBK - 1) / NBK;
-    const bool fwd = (int)blockIdx.x < T;
-    const int B = fwd ? blockIdx.x : 2 * T - 1 - blockIdx.x;
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int pair = xcd + 8 * (j / (2 * T)), x = j % (2 * T);
+    if (pair >= npairs) return;   // uniform over the workgroup, before any barrier
+    const long long zo = (long long)pair * zstride;
+    auto at = [zo](auto* p) {
+        return reinterpret_cast<decltype(p)>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)zo);
+    };
+    L = at(L);
+    dinv = at(dinv);
+    dsc = at(dsc);
+    b = at(b);
+    coef = at(coef);
+    flag = at(flag);
+    tsv = at(tsv);
+    tflag = at(tflag);
+    const bool fwd = x < T;
+    const int B = fwd ? x : 2 * T - 1 - x;
     const int r0 = B * NBK, nb = min(NBK, n - r0);
     const int i = threadIdx.x >> 2, p = threadIdx.x & 3;   // row, quarter of the columns
     double* ys = tsv;
@@ -589,8 +601,10 @@ hipError_t launch_chol_solve(const Geom& g, int n, const double* L, const double
     // publishes, with a short bound: each wait gives up, every block exits
     const int wait_gen = stall_test ? 0x7fffffff : gen;
     const int spin = stall_test ? kStallTestSpin : kSolveSpin;
-    hipLaunchKernelGGL(trsv_flow_kernel, dim3(2 * T, 1, g.nb), dim3(256), 0, st, n, L, dinv, dsc, rhs,
-                       coef, accumulate, flag, tsv, tflag, gen, wait_gen, spin, g.zs);
+    // 2T workgroups per pair, the pairs dealt to the XCDs (see the kernel)
+    const int rounds = (g.nb + 7) / 8;
+    hipLaunchKernelGGL(trsv_flow_kernel, dim3(8 * 2 * T * rounds), dim3(256), 0, st, n, L, dinv, dsc,
+                       rhs, coef, accumulate, flag, tsv, tflag, gen, wait_gen, spin, g.nb, g.zs);
     return hipGetLastError();
 }
 

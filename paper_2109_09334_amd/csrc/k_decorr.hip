@@ -104,7 +104,8 @@ __global__ void __launch_bounds__(512) colconv_kernel(Geom g, LinePlan lp, cx<T>
     cx<T> v[kElemsPerThread];
 #pragma unroll
     for (int e = 0; e < kElemsPerThread; ++e)   // rows >= n0: a Bluestein line's padding
-        v[e] = act && lt + e * lp.tl < n0 ? zc[(size_t)(lt + e * lp.tl) * g.hp] : mk(T(0), T(0));
+        v[e] = act && in_line<PL>(lt + e * lp.tl, n0) ? zc[(size_t)(lt + e * lp.tl) * g.hp]
+                                                      : mk(T(0), T(0));
     line_dft<-1, T, PL>(v, buf, lp, lt, twt);
     // the column's stamp row DFTs k_(s,a)(m) staged in the line's LDS buffer,
     // free between the two transforms (read from HBM where a short line's
@@ -123,7 +124,7 @@ __global__ void __launch_bounds__(512) colconv_kernel(Geom g, LinePlan lp, cx<T>
 #pragma unroll 1
         for (int e = 0; e < kElemsPerThread; ++e) {
             const int l = lt + e * lp.tl;
-            if (l >= n0) continue;
+            if (!in_line<PL>(l, n0)) continue;
             const cx<T> t1 = tw[l];   // W^l; W^(l a) by the recurrence t <- t W^l
             T gsum = T(0), hsum = T(0), kk = T(0);
 #pragma unroll 1
@@ -153,7 +154,7 @@ __global__ void __launch_bounds__(512) colconv_kernel(Geom g, LinePlan lp, cx<T>
     if (act) {
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e)
-            if (lt + e * lp.tl < n0) zc[(size_t)(lt + e * lp.tl) * g.hp] = v[e];
+            if (in_line<PL>(lt + e * lp.tl, n0)) zc[(size_t)(lt + e * lp.tl) * g.hp] = v[e];
     }
 }
 
@@ -173,7 +174,7 @@ hipError_t launch_colconv(const Geom& g, const LinePlan& lp, cx<T>* Z, const cx<
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
     dim3 grid((ncb + 127) / 128 * 128);
-    return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
+    return with_line_plan(lp, [&](auto pl) -> hipError_t {
         auto k = colconv_kernel<T, decltype(pl)>;
         if (lds > 65536) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),

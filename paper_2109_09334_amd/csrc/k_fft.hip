@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
             Tin la[kElemsPerThread], lb[kElemsPerThread];
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e) {
-                const int t = min(lt + e * lp.tl, n1 - 1);
+                const int t = pad_index<PL>(lt + e * lp.tl, n1);
                 la[e] = pa[t];
                 lb[e] = pb[t];
             }
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
                 const T c = coord<T>(lt + e * lp.tl, n1);
                 const T va = ipow_upto<kMaxDegree>(c, ea) * T((double)la[e] - qa);
                 const T vb = hasb ? ipow_upto<kMaxDegree>(c, eb) * T((double)lb[e] - qb) : T(0);
-                v[e] = lt + e * lp.tl < n1 ? mk(va, vb) : mk(T(0), T(0));
+                v[e] = in_line<PL>(lt + e * lp.tl, n1) ? mk(va, vb) : mk(T(0), T(0));
             }
         } else {
 #pragma unroll
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
         if (act) {
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e)
-                z[e] = zc[(size_t)min(lt + e * lp.tl, n0 - 1) * g.hp];
+                z[e] = zc[(size_t)pad_index<PL>(lt + e * lp.tl, n0) * g.hp];
         }
     }
     const int nw = jobs.nw[job];
@@ -146,12 +146,12 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
             }
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e)
-                v[e] = act && lt + e * lp.tl < n0 ? z[e] : mk(T(0), T(0));
+                v[e] = act && in_line<PL>(lt + e * lp.tl, n0) ? z[e] : mk(T(0), T(0));
         } else {
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e)
-                v[e] = act && li + e * lp.tl < n0
-                           ? cscale(zc[(size_t)min(li + e * lp.tl, n0 - 1) * g.hp], ipow(c0[e], i))
+                v[e] = act && in_line<PL>(li + e * lp.tl, n0)
+                           ? cscale(zc[(size_t)pad_index<PL>(li + e * lp.tl, n0) * g.hp], ipow(c0[e], i))
                            : mk(T(0), T(0));
         }
         line_dft<-1, T, PL>(v, buf, lp, li, twt);
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
             cx<T>* xo = X + ((size_t)jobs.spec[job][i] * g.h + m) * n0;
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e)
-                if (li + e * lp.tl < n0) xo[li + e * lp.tl] = v[e];
+                if (in_line<PL>(li + e * lp.tl, n0)) xo[li + e * lp.tl] = v[e];
         }
     }
 }
@@ -193,11 +193,11 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) {
             const int m = lt + e * lp.tl;   // >= n1: a Bluestein line's padding
-            const int mf = m < g.h ? m : (m < n1 ? n1 - m : 0);
+            const int mf = m < g.h ? m : (in_line<PL>(m, n1) ? n1 - m : 0);
             cx<T> a = A[mf], b = B[mf];
             if (m >= g.h) { a.im = -a.im; b.im = -b.im; }
             if (m == 0 || 2 * m == n1) { a.im = T(0); b.im = T(0); }
-            v[e] = m < n1 ? mk(a.re - b.im, a.im + b.re) : mk(T(0), T(0));
+            v[e] = in_line<PL>(m, n1) ? mk(a.re - b.im, a.im + b.re) : mk(T(0), T(0));
         }
     } else {
 #pragma unroll
@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
                 double y[kChunk];
 #pragma unroll
                 for (int q = 0; q < kChunk; ++q)
-                    y[q] = sky[(size_t)r * n1 + min(lt + (e0 + q) * lp.tl, n1 - 1)];
+                    y[q] = sky[(size_t)r * n1 + pad_index<PL>(lt + (e0 + q) * lp.tl, n1)];
 #pragma unroll
                 for (int q = 0; q < kChunk; ++q) {
                     ba[q] += pa * y[q];
@@ -242,14 +242,14 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
             }
             if (ra)
 #pragma unroll
-                for (int q = 0; q < kChunk; ++q) ba[q] = ra[min(lt + (e0 + q) * lp.tl, n1 - 1)];
+                for (int q = 0; q < kChunk; ++q) ba[q] = ra[pad_index<PL>(lt + (e0 + q) * lp.tl, n1)];
             if (rb)
 #pragma unroll
-                for (int q = 0; q < kChunk; ++q) bb[q] = rb[min(lt + (e0 + q) * lp.tl, n1 - 1)];
+                for (int q = 0; q < kChunk; ++q) bb[q] = rb[pad_index<PL>(lt + (e0 + q) * lp.tl, n1)];
 #pragma unroll
             for (int q = 0; q < kChunk; ++q) {
                 const int x1 = lt + (e0 + q) * lp.tl;
-                if (x1 < n1) {
+                if (in_line<PL>(x1, n1)) {
                     d[(size_t)xa * n1 + x1] = Tout((double)v[e0 + q].re * inv - ba[q]);
                     d[(size_t)xb * n1 + x1] = Tout((double)v[e0 + q].im * inv - bb[q]);
                 }
@@ -272,12 +272,13 @@ __global__ void __launch_bounds__(512) fft_lines_kernel(LinePlan lp, int nlines,
     cx<T> v[kElemsPerThread];
 #pragma unroll
     for (int e = 0; e < kElemsPerThread; ++e)
-        v[e] = act && lt + e * lp.tl < nl ? in[(size_t)ln * nl + lt + e * lp.tl] : mk(T(0), T(0));
+        v[e] = act && in_line<PL>(lt + e * lp.tl, nl) ? in[(size_t)ln * nl + lt + e * lp.tl]
+                                                     : mk(T(0), T(0));
     line_dft<S, T, PL>(v, buf, lp, lt, twt);
     if (act)
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e)
-            if (lt + e * lp.tl < nl) out[(size_t)ln * nl + lt + e * lp.tl] = v[e];
+            if (in_line<PL>(lt + e * lp.tl, nl)) out[(size_t)ln * nl + lt + e * lp.tl] = v[e];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -301,7 +302,7 @@ hipError_t launch_rowfwd(const Geom& g, const LinePlan& lp, const RowSources& sr
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     const int nlines = src.rowpair ? g.n0 / 2 : g.n0;
     dim3 grid((nlines + lp.lpw - 1) / lp.lpw, 1, g.nb);
-    return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
+    return with_line_plan(lp, [&](auto pl) -> hipError_t {
         auto k = rowfwd_kernel<T, Tin, decltype(pl)>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
@@ -317,7 +318,7 @@ hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs,
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
     dim3 grid((ncb + 127) / 128 * 128 * jobs.narr, 1, g.nb);
-    return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
+    return with_line_plan(lp, [&](auto pl) -> hipError_t {
         auto k = colfwd_kernel<T, decltype(pl)>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
@@ -331,7 +332,7 @@ hipError_t launch_rowinv(const Geom& g, const LinePlan& lp, const cx<T>* Dt, IoR
                          const double* sky, const cx<T>* twt, hipStream_t st) {
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     dim3 grid((g.n0 / 2 + lp.lpw - 1) / lp.lpw, 1, g.nb);
-    return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
+    return with_line_plan(lp, [&](auto pl) -> hipError_t {
         auto k = rowinv_kernel<T, Tout, decltype(pl)>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
@@ -345,7 +346,7 @@ hipError_t launch_fft_lines(const LinePlan& lp, int nlines, int sign, const cx<T
                             const cx<T>* twt, hipStream_t st) {
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     dim3 grid((nlines + lp.lpw - 1) / lp.lpw);
-    return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
+    return with_line_plan(lp, [&](auto pl) -> hipError_t {
         auto k = sign < 0 ? fft_lines_kernel<T, -1, decltype(pl)> : fft_lines_kernel<T, 1, decltype(pl)>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;

@@ -67,8 +67,8 @@ __global__ void __launch_bounds__(512) lagcol_kernel(Geom g, LinePlan lp, int p0
 #pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) {
             const int l = lt + e * lp.tl;   // >= n0: a Bluestein line's padding
-            const int lc = min(l, n0 - 1);
-            v[e] = l < n0 ? cmulc(A[lc], B[lc]) : mk(T(0), T(0));
+            const int lc = pad_index<PL>(l, n0);
+            v[e] = in_line<PL>(l, n0) ? cmulc(A[lc], B[lc]) : mk(T(0), T(0));
         }
     } else {
 #pragma unroll
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(512) lagcol_kernel(Geom g, LinePlan lp, int p0
         for (int e = 0; e < kElemsPerThread; ++e) {
             const int l = lt + e * lp.tl;   // lag d0 = l or l - N0
             const int d0 = l <= K ? l : l - n0;
-            if (l < n0 && d0 >= -K && d0 <= K)
+            if (in_line<PL>(l, n0) && d0 >= -K && d0 <= K)
                 Cl[((size_t)p * g.D0 + d0 + 2 * g.w0) * g.hp + m] = v[e];
         }
     }
@@ -473,7 +473,7 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
     dim3 grid((ncb + 7) / 8 * 8 * (p1 - p0), 1, g.nb);
-    return with_line_plan(lp.n, [&](auto pl) -> hipError_t {
+    return with_line_plan(lp, [&](auto pl) -> hipError_t {
         auto k = lagcol_kernel<T, decltype(pl)>;
         if (lds > 65536) {
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),

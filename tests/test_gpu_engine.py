@@ -319,3 +319,33 @@ def test_batch_of_bluestein_pairs_equals_alone(sfft):
         torch.cuda.synchronize()
         for k, (t, co, do) in enumerate(jobs):
             assert torch.equal(co, refs[k][0]) and torch.equal(do, refs[k][1]), k
+
+
+def test_many_slots_run_their_solves_concurrently(sfft):
+    """Sixteen slots with batches of two: the dataflow triangular solves of
+    many requests run at once, interleaved with every other stage, while
+    their workgroups are spread over the XCDs in whatever order the hardware
+    dispatches them. Every request must succeed and equal its direct call
+    bit for bit, in both forms."""
+    shapes = [(128, 128, 3, 2, 2), (256, 256, 5, 2, 2), (192, 256, 4, 1, 2), (96, 128, 3, 2, 1)]
+    with sfft.Context(0) as eager, sfft.Context(0) as ctx:
+        ctx.engine_config(16, 2)
+        refs, jobs = {}, []
+        for rep in range(6):
+            for k, (n0, n1, w, dk, db) in enumerate(shapes):
+                for pr in (sfft.MIXED, sfft.FP64):
+                    p = sfft.Params(n0, n1, w, w, dk, db, 0, pr, sfft.F32)
+                    R, S = _inputs(1200 + 10 * k + rep % 2, n0, n1, w, dk, db)
+                    key = (k, pr, rep % 2)
+                    if key not in refs:
+                        c, d = eager.run(p, R, S)
+                        eager.sync()
+                        refs[key] = (c.clone(), d.clone())
+                    co = torch.empty(p.num_unknowns, dtype=torch.float64, device="cuda")
+                    do = torch.empty((n0, n1), dtype=torch.float32, device="cuda")
+                    jobs.append((key, ctx.submit(p, R, S, R, S, co, do), co, do, R, S))
+        for key, t, co, do, _, _ in jobs:
+            assert ctx.wait(t) == sfft.OK, key
+        torch.cuda.synchronize()
+        for key, t, co, do, _, _ in jobs:
+            assert torch.equal(co, refs[key][0]) and torch.equal(do, refs[key][1]), key
