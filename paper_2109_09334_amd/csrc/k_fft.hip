@@ -95,11 +95,25 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
     }
 }
 
+// Adjacent columns per thread of the column pass: FP32 lines of up to 4096
+// points read the two columns m, m + 1 (m even) of a row as one 16-byte
+// load, which halves the L1 -> L2 requests of the row-strided column reads.
+// FP64, longer and Bluestein lines hold one (two would spill).
+template <typename T, typename PL>
+struct ColfwdCols {
+    static constexpr int value = 1;
+};
+template <int... R>
+struct ColfwdCols<float, RadixSeq<R...>> {
+    static constexpr int value = SeqProd<R...>::value <= 4096 ? 2 : 1;
+};
+
 template <typename T, typename PL>
 __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJobs jobs,
                                                       const cx<T>* __restrict__ Z,
                                                       cx<T>* __restrict__ X,
                                                       const cx<T>* __restrict__ twt) {
+    constexpr int NC = ColfwdCols<T, PL>::value;
     cx<T>* lds = lds_base<T>();
     Z = zoff(Z, g.zs);
     X = zoff(X, g.zs);
@@ -107,26 +121,36 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
     // Block -> (column block, job): workgroups are dealt to the 8 XCDs round
     // robin, so groups of 16 adjacent column blocks are kept on one XCD, where
     // their strided row reads share L2 lines.
-    const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
+    const int ncb = (g.h + NC * lp.lpw - 1) / (NC * lp.lpw);
     const int per_xcd = (ncb + 127) / 128 * 16;   // column blocks per XCD per job
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
     const int job = slot / per_xcd, r = slot - job * per_xcd;
     const int cb = 16 * (8 * (r >> 4) + xcd) + (r & 15);
-    const int m = cb * lp.lpw + line;
+    const int m = (cb * lp.lpw + line) * NC;   // the thread's first column
     const bool act = m < g.h;
     const int n0 = g.n0;
     const int a = jobs.arr[job];
     cx<T>* buf = lds + line * line_lds_elems(lp.n);
-    // FP32 holds the column across the weights (z = c0^i Z_a); FP64 reads
-    // it again per weight (from L2 after the first) to stay clear of spills
+    // FP32 holds the columns across the weights (z = c0^i Z_a); FP64 reads
+    // its column again per weight (from L2 after the first) to stay clear of
+    // spills
     constexpr bool kHold = sizeof(T) == 4;
     const cx<T>* zc = Z + (size_t)a * n0 * g.hp + m;
-    cx<T> z[kHold ? kElemsPerThread : 1];
+    cx<T> z[NC][kHold ? kElemsPerThread : 1];
     if constexpr (kHold) {
         if (act) {
 #pragma unroll
-            for (int e = 0; e < kElemsPerThread; ++e)
-                z[e] = zc[(size_t)pad_index<PL>(lt + e * lp.tl, n0) * g.hp];
+            for (int e = 0; e < kElemsPerThread; ++e) {
+                const size_t o = (size_t)pad_index<PL>(lt + e * lp.tl, n0) * g.hp;
+                if constexpr (NC == 2) {
+                    // columns m, m + 1 < hp (m and hp even: 16-byte aligned)
+                    const float4 q = *reinterpret_cast<const float4*>(zc + o);
+                    z[0][e] = mk(q.x, q.y);
+                    z[1][e] = mk(q.z, q.w);
+                } else {
+                    z[0][e] = zc[o];
+                }
+            }
         }
     }
     const int nw = jobs.nw[job];
@@ -138,28 +162,37 @@ __global__ void __launch_bounds__(512) colfwd_kernel(Geom g, LinePlan lp, ColJob
         // the thread index through an opaque zero: addresses are formed per
         // weight instead of held in registers across the loop
         const int li = lt + opaque_zero();
-        cx<T> v[kElemsPerThread];
         if constexpr (kHold) {
             if (i > 0) {
 #pragma unroll
-                for (int e = 0; e < kElemsPerThread; ++e) z[e] = cscale(z[e], c0[e]);
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int e = 0; e < kElemsPerThread; ++e) z[c][e] = cscale(z[c][e], c0[e]);
             }
-#pragma unroll
-            for (int e = 0; e < kElemsPerThread; ++e)
-                v[e] = act && in_line<PL>(lt + e * lp.tl, n0) ? z[e] : mk(T(0), T(0));
-        } else {
-#pragma unroll
-            for (int e = 0; e < kElemsPerThread; ++e)
-                v[e] = act && in_line<PL>(li + e * lp.tl, n0)
-                           ? cscale(zc[(size_t)pad_index<PL>(li + e * lp.tl, n0) * g.hp], ipow(c0[e], i))
-                           : mk(T(0), T(0));
         }
-        line_dft<-1, T, PL>(v, buf, lp, li, twt);
-        if (act) {
-            cx<T>* xo = X + ((size_t)jobs.spec[job][i] * g.h + m) * n0;
 #pragma unroll
-            for (int e = 0; e < kElemsPerThread; ++e)
-                if (in_line<PL>(li + e * lp.tl, n0)) xo[li + e * lp.tl] = v[e];
+        for (int c = 0; c < NC; ++c) {
+            const bool on = act && m + c < g.h;   // every thread takes part in the transform
+            cx<T> v[kElemsPerThread];
+            if constexpr (kHold) {
+#pragma unroll
+                for (int e = 0; e < kElemsPerThread; ++e)
+                    v[e] = on && in_line<PL>(lt + e * lp.tl, n0) ? z[c][e] : mk(T(0), T(0));
+            } else {
+#pragma unroll
+                for (int e = 0; e < kElemsPerThread; ++e)
+                    v[e] = on && in_line<PL>(li + e * lp.tl, n0)
+                               ? cscale(zc[(size_t)pad_index<PL>(li + e * lp.tl, n0) * g.hp + c],
+                                        ipow(c0[e], i))
+                               : mk(T(0), T(0));
+            }
+            line_dft<-1, T, PL>(v, buf, lp, li, twt);
+            if (on) {
+                cx<T>* xo = X + ((size_t)jobs.spec[job][i] * g.h + m + c) * n0;
+#pragma unroll
+                for (int e = 0; e < kElemsPerThread; ++e)
+                    if (in_line<PL>(li + e * lp.tl, n0)) xo[li + e * lp.tl] = v[e];
+            }
         }
     }
 }
@@ -316,9 +349,10 @@ template <typename T>
 hipError_t launch_colfwd(const Geom& g, const LinePlan& lp, const ColJobs& jobs, const cx<T>* Z,
                          cx<T>* X, const cx<T>* twt, hipStream_t st) {
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
-    const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
-    dim3 grid((ncb + 127) / 128 * 128 * jobs.narr, 1, g.nb);
     return with_line_plan(lp, [&](auto pl) -> hipError_t {
+        const int cols = ColfwdCols<T, decltype(pl)>::value * lp.lpw;   // columns per workgroup
+        const int ncb = (g.h + cols - 1) / cols;
+        dim3 grid((ncb + 127) / 128 * 128 * jobs.narr, 1, g.nb);
         auto k = colfwd_kernel<T, decltype(pl)>;
         hipError_t e = set_lds(k, lds);
         if (e != hipSuccess) return e;
