@@ -46,24 +46,25 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
         // the thread index through an opaque zero: addresses are formed per
         // packed pair instead of held in registers across the loop
         const int lt = lt0 + opaque_zero();
-        cx<T> v[kElemsPerThread];
+        // both rows loaded unconditionally (pb is a valid row when the pair
+        // has no second source), then the weights applied (a Bluestein line's
+        // padding, t >= n1, loads a valid pixel and is zeroed after)
+        const Tin* pa = (src.img[ia] ? img1 : img0) + (size_t)xa * n1;
+        const Tin* pb = (hasb && src.img[ib] ? img1 : img0) + (size_t)xb * n1;
+        Tin la[kElemsPerThread], lb[kElemsPerThread];
         if (act) {
-            const Tin* pa = (src.img[ia] ? img1 : img0) + (size_t)xa * n1;
-            const Tin* pb = (hasb && src.img[ib] ? img1 : img0) + (size_t)xb * n1;
-            const int ea = src.pow[ia], eb = hasb ? src.pow[ib] : 0;
-            const double qa = src.ped[ia] >= 0 ? ped[src.ped[ia]] : 0.0;
-            const double qb = hasb && src.ped[ib] >= 0 ? ped[src.ped[ib]] : 0.0;
-            // both rows loaded unconditionally (pb is a valid row when the
-            // pair has no second source), then the weights applied
-            // (a Bluestein line's padding, t >= n1, loads a valid pixel and
-            // is zeroed after)
-            Tin la[kElemsPerThread], lb[kElemsPerThread];
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e) {
                 const int t = pad_index<PL>(lt + e * lp.tl, n1);
                 la[e] = pa[t];
                 lb[e] = pb[t];
             }
+        }
+        cx<T> v[kElemsPerThread];
+        if (act) {
+            const int ea = src.pow[ia], eb = hasb ? src.pow[ib] : 0;
+            const double qa = src.ped[ia] >= 0 ? ped[src.ped[ia]] : 0.0;
+            const double qb = hasb && src.ped[ib] >= 0 ? ped[src.ped[ib]] : 0.0;
 #pragma unroll
             for (int e = 0; e < kElemsPerThread; ++e) {
                 const T c = coord<T>(lt + e * lp.tl, n1);
@@ -84,11 +85,30 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
         if (act) {
             cx<T>* za = Z + ((size_t)src.out[ia] * g.n0 + xa) * g.hp;
             cx<T>* zb = Z + ((size_t)(hasb ? src.out[ib] : 0) * g.n0 + xb) * g.hp;
+            auto half = [&](int m, cx<T>& ra, cx<T>& rb) {
+                const cx<T> x = buf[lpad(m)], y = buf[lpad(m == 0 ? 0 : n1 - m)];
+                ra = mk((x.re + y.re) * T(0.5), (x.im - y.im) * T(0.5));
+                rb = mk((x.im + y.im) * T(0.5), (y.re - x.re) * T(0.5));
+            };
+            if constexpr (sizeof(T) == 4) {
+                // bins m, m + 1 (m even) with one 16-byte store per row; the
+                // last pair may write bin h into the row padding (h odd)
 #pragma unroll 2
-            for (int m = lt; m < g.h; m += lp.tl) {
-                const cx<T> a = buf[lpad(m)], b = buf[lpad(m == 0 ? 0 : n1 - m)];
-                za[m] = mk((a.re + b.re) * T(0.5), (a.im - b.im) * T(0.5));
-                if (hasb) zb[m] = mk((a.im + b.im) * T(0.5), (b.re - a.re) * T(0.5));
+                for (int m = 2 * lt; m < g.h; m += 2 * lp.tl) {
+                    cx<T> a0, b0, a1, b1;
+                    half(m, a0, b0);
+                    half(m + 1, a1, b1);
+                    *reinterpret_cast<float4*>(za + m) = make_float4(a0.re, a0.im, a1.re, a1.im);
+                    if (hasb) *reinterpret_cast<float4*>(zb + m) = make_float4(b0.re, b0.im, b1.re, b1.im);
+                }
+            } else {
+#pragma unroll 2
+                for (int m = lt; m < g.h; m += lp.tl) {
+                    cx<T> ra, rb;
+                    half(m, ra, rb);
+                    za[m] = ra;
+                    if (hasb) zb[m] = rb;
+                }
             }
         }
         __syncthreads();

@@ -207,6 +207,31 @@ def test_separate_calls_match_run(sfft, ctx, prec):
     assert rms <= (1e-10 if prec == "fp64" else 1e-5) * 10.0
 
 
+@pytest.mark.parametrize("prec,dtype", [("fp64", "f64"), ("fp64", "f32"), ("mixed", "f32")])
+def test_unaligned_caller_images_match_aligned(sfft, ctx, prec, dtype):
+    """Row passes read 16-byte aligned image rows with vector loads and fall
+    back to element loads otherwise: images that start one element past a
+    16-byte boundary must give the same bits as aligned copies."""
+    n0, n1, w, dk, db = 96, 128, 3, 2, 2
+    r, s = _pair(11, n0, n1, w, dk, db, 0)
+    pr = sfft.FP64 if prec == "fp64" else sfft.MIXED
+    dt, tdt = (sfft.F64, torch.float64) if dtype == "f64" else (sfft.F32, torch.float32)
+    p = _params(sfft, n0, n1, w, w, dk, db, 0, pr, dt)
+    R, S = _dev(r, tdt), _dev(s, tdt)
+    coef, d = ctx.run(p, R, S)
+    ctx.sync()
+    flat_r = torch.zeros(n0 * n1 + 1, dtype=tdt, device="cuda")
+    flat_s = torch.zeros(n0 * n1 + 1, dtype=tdt, device="cuda")
+    Ru, Su = flat_r[1:].view(n0, n1), flat_s[1:].view(n0, n1)
+    Ru.copy_(R)
+    Su.copy_(S)
+    assert Ru.data_ptr() % 16 != 0 and Su.data_ptr() % 16 != 0
+    coef_u, d_u = ctx.run(p, Ru, Su)
+    ctx.sync()
+    assert torch.equal(coef, coef_u)
+    assert torch.equal(d, d_u)
+
+
 APPLY_CASES = [
     # n0, n1, w, dk, db
     (64, 64, 2, 1, 1),
