@@ -146,6 +146,121 @@ __device__ __forceinline__ void tile_update(int n, double* __restrict__ L, int k
     }
 }
 
+// Broadcast of lane `src`'s value to the wave.
+__device__ __forceinline__ double bcast(double v, int src) {
+    const long long u = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffff), src);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 16 x 16 block of P Q^T over the 16 columns c0..c0+15 on the matrix cores:
+//   acc[q] = sum_k P[pr + lane/16 + 4 q][c0 + k] Q[qr + lane%16][c0 + k].
+__device__ __forceinline__ dbl4 mfma16(const double (*P)[NBK + 1], int pr,
+                                       const double (*Q)[NBK + 1], int qr, int c0, int lane) {
+    const int lr = lane & 15, lk = lane >> 4;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        const int cc = c0 + 4 * kk + lk;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(P[pr + lr][cc], Q[qr + lr][cc], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Cholesky factor of the 64 x 64 block D (lower part, identity padding) and
+// the solve of the na rows of A against it (A := A L_D^-T), in place in LDS,
+// by 16-column blocks jb:
+//  (1) wave 0 factorises D_jj = L_jj L_jj^T in registers (lane i holds row
+//      i; the pivot and the column below it are broadcast by readlane): the
+//      16 dependent steps need no barrier;
+//  (2) every row below the block in D and every row of A is solved against
+//      L_jj, one row per thread (y_j = (a_j - sum_(k<j) y_k L_jk) / L_jj);
+//  (3) the 16 x 16 blocks right of the column block take the rank-16 update
+//      (D_IJ -= L_Ij L_Jj^T for J <= I, A_IJ -= Y_I L_Jj^T) on the FP64
+//      matrix cores, one block per wave at a time.
+// A pivot that is not positive and finite sets the flag and is taken as 1.
+// Every thread of the workgroup calls it (it synchronises).
+__device__ __forceinline__ void factor_panel(double (*D)[NBK + 1], double (*A)[NBK + 1], int na,
+                                             int* flag) {
+    __shared__ double rdiag[16];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll 1
+    for (int jb = 0; jb < 4; ++jb) {
+        const int c0 = 16 * jb;
+        if (wv == 0) {   // (1)
+            const int li = lane & 15;
+            double r[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) r[c] = D[c0 + li][c0 + c];
+            bool bad = false, nonfin = false;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                double piv = bcast(r[j], j);
+                if (!(piv > 0.0) || !isfinite(piv)) {
+                    bad = true;
+                    nonfin |= !isfinite(piv);
+                    piv = 1.0;
+                }
+                const double inv = rsqrt(piv), ljj = piv * inv;
+                r[j] = li > j ? r[j] * inv : (li == j ? ljj : 0.0);
+#pragma unroll
+                for (int kc = j + 1; kc < 16; ++kc) r[kc] -= r[j] * bcast(r[j], kc);
+            }
+            if (lane < 16) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) D[c0 + lane][c0 + c] = c <= lane ? r[c] : 0.0;
+                rdiag[lane] = 1.0 / r[lane];
+            }
+            if (bad && lane == 0) atomicOr(flag, nonfin ? kFlagNonFinite : kFlagNotSpd);
+        }
+        __syncthreads();
+        // (2): rows c0+16 .. 63 of D, then the na rows of A
+        const int nd = NBK - c0 - 16;
+        for (int t = threadIdx.x; t < nd + na; t += kStepThreads) {
+            double* row = t < nd ? D[c0 + 16 + t] : A[t - nd];
+            double y[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                double v = row[c0 + j];
+#pragma unroll
+                for (int kc = 0; kc < j; ++kc) v -= y[kc] * D[c0 + j][c0 + kc];
+                y[j] = v * rdiag[j];
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) row[c0 + j] = y[j];
+        }
+        __syncthreads();
+        if (jb == 3) break;
+        // (3): D blocks (I, J), jb < J <= I < 4, then A blocks (I, J), I < 4, J > jb
+        const int nj = 3 - jb, ndb = nj * (nj + 1) / 2, nab = 4 * nj;
+        for (int bi = wv; bi < ndb + nab; bi += kStepWaves) {
+            int I, J;
+            const bool isd = bi < ndb;
+            if (isd) {
+                int rem = bi;
+                I = 0;
+                while (rem > I) {
+                    rem -= I + 1;
+                    ++I;
+                }
+                J = rem + jb + 1;
+                I += jb + 1;
+            } else {
+                I = (bi - ndb) / nj;
+                J = jb + 1 + (bi - ndb) % nj;
+            }
+            const dbl4 acc = isd ? mfma16(D, 16 * I, D, 16 * J, c0, lane)
+                                 : mfma16(A, 16 * I, D, 16 * J, c0, lane);
+            double (*T)[NBK + 1] = isd ? D : A;
+            const int jc = 16 * J + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) T[16 * I + (lane >> 4) + 4 * q][jc] -= acc[q];
+        }
+        __syncthreads();
+    }
+}
+
 // Step k of the right-looking factorisation, with the trailing update of
 // step k - 1 folded in: one launch per 64-column panel (kb = 64 k).
 //  * Workgroups b < T - k (T = number of 64-blocks) work on panel k, row
@@ -156,14 +271,11 @@ __device__ __forceinline__ void tile_update(int n, double* __restrict__ L, int k
 //    FP64 matrix cores. Then every one factorises the diagonal block D;
 //    workgroup 0 stores it in dfac (copied into L after the last step),
 //    workgroup b >= 1 also solves its row block X L_D^T = A.
-//    Factor and solve are one right-looking pass over the 64 columns: 512
-//    threads own 2x4 register tiles (rows ty + 32 a, columns tx + 16 b) of D
-//    and A; the raw column j is published through LDS (double buffered, one
-//    barrier per column) and every thread scales it by the pivot itself. The
-//    column group bj = j / 16 is unrolled, so tiles are addressed statically
-//    and the updates skip the groups left of the pivot. The pass is a chain
-//    of 64 dependent column steps (LDS round trip, barrier, pivot inverse
-//    square root, FMAs): about 1000 cycles each, the floor of this design.
+//    Factor and solve run on D and A in LDS, 16 columns at a time
+//    (factor_panel): one wave factorises the 16 x 16 diagonal block in
+//    registers, the rows below it and the rows of A are solved against it
+//    one row per thread, and the trailing 16 x 16 blocks take the rank-16
+//    update on the matrix cores; three barriers per 16 columns.
 //  * The other workgroups give the tiles (I, J), I >= J > k, of the trailing
 //    matrix panel k-1's update.
 // After the launch column block k is final and every tile right of it has
@@ -178,8 +290,6 @@ __global__ void __launch_bounds__(kStepThreads) chol_step_kernel(int n, double* 
     constexpr int RA = NBK / RY;            // rows per thread
     __shared__ double PI[NBK][NBK + 1];
     __shared__ double PJ[NBK][NBK + 1];
-    __shared__ double colD[2][NBK];
-    __shared__ double colA[2][NBK];
     const int T = (n + NBK - 1) / NBK;
     const int kb = k * NBK;
     const int npan = T - k;
@@ -241,105 +351,29 @@ __global__ void __launch_bounds__(kStepThreads) chol_step_kernel(int n, double* 
                 x[a][b] -= PI[ty + RY * a][tx + 16 * b];
             }
     }
-    // Column j is published in buffer j & 1 by its owners (tx == j % 16) as
-    // soon as its last update is done: right after the update of its own
-    // 16-column group, before the FMAs of the groups to the right, so the
-    // LDS write overlaps them. Double buffering keeps the readers of column
-    // j - 1 (all past the barrier of column j) clear of the write of j + 1.
-    if (tx == 0) {
-#pragma unroll
-        for (int a = 0; a < RA; ++a) {
-            colD[0][ty + RY * a] = d[a][0];
-            colA[0][ty + RY * a] = x[a][0];
-        }
-    }
-#pragma unroll
-    for (int bj = 0; bj < 4; ++bj) {
-#pragma unroll 1
-        for (int jj = 0; jj < 16; ++jj) {
-            const int j = 16 * bj + jj;
-            if (j >= nb) break;   // uniform over the workgroup
-            const int buf = j & 1;
-            const bool owner = tx == jj;
-            __syncthreads();
-            // all LDS reads first (unconditional, so they issue together)
-            double cd[RA], cx[RA], cc[4];
-            double piv = colD[buf][j];
-#pragma unroll
-            for (int a = 0; a < RA; ++a) {
-                cd[a] = colD[buf][ty + RY * a];
-                cx[a] = colA[buf][ty + RY * a];
-            }
-#pragma unroll
-            for (int b = 0; b < 4; ++b) cc[b] = colD[buf][tx + 16 * b];
-            if (!(piv > 0.0) || !isfinite(piv)) {
-                if (threadIdx.x == 0) atomicOr(flag, isfinite(piv) ? kFlagNotSpd : kFlagNonFinite);
-                piv = 1.0;
-            }
-            const double inv = rsqrt(piv), ljj = piv * inv;
-            double li[RA], xi[RA], lc[4];
-#pragma unroll
-            for (int a = 0; a < RA; ++a) {
-                li[a] = ty + RY * a > j ? cd[a] * inv : 0.0;
-                xi[a] = cx[a] * inv;
-            }
-#pragma unroll
-            for (int b = 0; b < 4; ++b) lc[b] = tx + 16 * b > j ? cc[b] * inv : 0.0;
-            if (owner) {
-#pragma unroll
-                for (int a = 0; a < RA; ++a) {
-                    const int i = ty + RY * a;
-                    d[a][bj] = i == j ? ljj : (i > j ? li[a] : 0.0);
-                    x[a][bj] = xi[a];
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < RA; ++a) {
-                d[a][bj] -= li[a] * lc[bj];
-                x[a][bj] -= xi[a] * lc[bj];
-            }
-            if (jj < 15 && tx == jj + 1) {
-#pragma unroll
-                for (int a = 0; a < RA; ++a) {
-                    colD[buf ^ 1][ty + RY * a] = d[a][bj];
-                    colA[buf ^ 1][ty + RY * a] = x[a][bj];
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < RA; ++a)
-#pragma unroll
-                for (int b = bj + 1; b < 4; ++b) {
-                    d[a][b] -= li[a] * lc[b];
-                    x[a][b] -= xi[a] * lc[b];
-                }
-            if (bj < 3 && jj == 15 && tx == 0) {   // next column opens group bj + 1
-                const int bn = bj < 3 ? bj + 1 : 3;
-#pragma unroll
-                for (int a = 0; a < RA; ++a) {
-                    colD[buf ^ 1][ty + RY * a] = d[a][bn];
-                    colA[buf ^ 1][ty + RY * a] = x[a][bn];
-                }
-            }
-        }
-    }
-    if (blockIdx.x == 0) {
-        double* out = dfac + (size_t)k * NBK * NBK;
-#pragma unroll
-        for (int a = 0; a < RA; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int i = ty + RY * a, c = tx + 16 * b;
-                if (i < nb && c < nb) out[i * NBK + c] = c <= i ? d[a][b] : 0.0;
-            }
-        return;
-    }
+    // D (lower part; identity past nb) and A into LDS for the blocked pass
 #pragma unroll
     for (int a = 0; a < RA; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int i = ty + RY * a, c = tx + 16 * b;
-            if (i < nr && c < nb) L[(size_t)(r0 + i) * n + kb + c] = x[a][b];
+            PJ[i][c] = (i < nb && c < nb) ? d[a][b] : (i == c ? 1.0 : 0.0);
+            PI[i][c] = x[a][b];
         }
+    __syncthreads();
+    factor_panel(PJ, PI, blockIdx.x == 0 ? 0 : nr, flag);
+    if (blockIdx.x == 0) {
+        double* out = dfac + (size_t)k * NBK * NBK;
+        for (int t = threadIdx.x; t < NBK * NBK; t += kStepThreads) {
+            const int i = t >> 6, c = t & 63;
+            if (i < nb && c < nb) out[i * NBK + c] = c <= i ? PJ[i][c] : 0.0;
+        }
+        return;
+    }
+    for (int t = threadIdx.x; t < NBK * NBK; t += kStepThreads) {
+        const int i = t >> 6, c = t & 63;
+        if (i < nr && c < nb) L[(size_t)(r0 + i) * n + kb + c] = PI[i][c];
+    }
 }
 
 // After the last panel, per diagonal block B: the factor held in dfac goes
