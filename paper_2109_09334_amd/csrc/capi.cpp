@@ -256,13 +256,18 @@ static hipError_t make_twiddles(int n, bool mixed, Twiddles& t) {
     for (int k = 0; k < m; ++k) bh[k] = {(double)(b[k].real() / m), (double)(b[k].imag() / m)};
     e = upload<double>(chirp, &t.chirp);   // FP64 in both forms
     if (e) return e;
-    return upload<double>(bh, &t.bhat);
+    e = upload<double>(bh, &t.bhat);
+    if (e) return e;
+    std::vector<cx<double>> wm(m);
+    for (int k = 0; k < m; ++k) wm[k] = W(k, m);
+    return mixed ? upload<float>(wm, &t.twm) : upload<double>(wm, &t.twm);
 }
 
 static void free_twiddles(Twiddles& t) {
     if (t.chirp) (void)hipFree(t.chirp);
     if (t.bhat) (void)hipFree(t.bhat);
-    t.chirp = t.bhat = nullptr;
+    if (t.twm) (void)hipFree(t.twm);
+    t.chirp = t.bhat = t.twm = nullptr;
     if (t.tw) (void)hipFree(t.tw);
     if (t.twt) (void)hipFree(t.twt);
     t.twt = nullptr;
@@ -328,8 +333,10 @@ int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out,
     if (rc) return rc;
     pl->lp0.chirp = pl->t0.chirp;
     pl->lp0.bhat = pl->t0.bhat;
+    pl->lp0.twm = pl->t0.twm;
     pl->lp1.chirp = pl->t1.chirp;
     pl->lp1.bhat = pl->t1.bhat;
+    pl->lp1.twm = pl->t1.twm;
     char* base = nullptr;
     if (hipMalloc(&base, bytes) != hipSuccess) return SFFT_E_NOMEM;
     carve(pl->ws, pl->g, mixed ? 8 : 16, mixed ? 4 : 8, base);
@@ -1072,6 +1079,7 @@ int sfft_fft_lines(sfft_ctx* ctx, int n, int lines, int sign, int dtype, const v
     LinePlan lp = make_line_plan(n);
     lp.chirp = t.chirp;
     lp.bhat = t.bhat;
+    lp.twm = t.twm;
     hipError_t e;
     if (dtype == SFFT_F32)
         e = launch_fft_lines<float>(lp, lines, sign, (const cx<float>*)in, (cx<float>*)out,

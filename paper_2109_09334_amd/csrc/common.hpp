@@ -119,6 +119,9 @@ struct LinePlan {
     // cx<double>.
     const void* chirp;
     const void* bhat;
+    // Bluestein lines: e^(-2 pi i t / n), t < n, in the compute type (the
+    // transform length's twiddles; null otherwise)
+    const void* twm;
 };
 
 // Geometry of one subtraction problem (Eq. 1-6): image N0 x N1 (x = axis 0),

@@ -363,6 +363,92 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
     }
 }
 
+// Pruned inverse along axis 0 for a Bluestein line (N0 = nl not 16 x its
+// threads per line, transform length M = 16 TL): the lags of the inverse
+// DFT of length nl, C(d0) = sum_l P(l) e^(+2 pi i l d0 / nl), |d0| <= K, are
+// conj of the forward DFT of conj(P) at k = d0 mod nl. In the Bluestein form
+// that forward DFT is F(k) = conj(c_k) z(k), z = IDFT_M(DFT_M(a) bhat) with
+// a_t = conj(c_t) conj(P(t)): one forward M-point transform per product, and
+// z only at k in [0, K] and [nl - K, nl), by the decimation of
+// lagcol_tail_kernel (thread j holds DFT_M(a) bhat at j + TL q, q < 16; the
+// radix-16 inverse over q; each 16-slot block of k summed over the line
+// with twiddles e^(+2 pi i j k / M), the wave transpose-reduce, and the
+// waves' sums through LDS). Then C(d0) = c_k conj(z(k)). The chirp products
+// are formed in FP64, as in line_dft.
+template <typename T, typename PL>
+__global__ void __launch_bounds__(512) lagcol_chirp_kernel(Geom g, LinePlan lp, int p0, int np,
+                                                            int sslot, const cx<T>* __restrict__ X,
+                                                            cx<T>* __restrict__ Cl,
+                                                            const cx<T>* __restrict__ twt) {
+    using P = typename PL::plan;
+    cx<T>* lds = lds_base_l<T>();
+    X = zoff(X, g.zs);
+    Cl = zoff(Cl, g.zs);
+    const int tl = lp.tl;
+    const int line = threadIdx.x / tl, lt = threadIdx.x - line * tl;
+    const int lane = threadIdx.x & 63, nwl = tl >> 6, wl = (threadIdx.x >> 6) - line * nwl;
+    // block -> (column block, product) as in lagcol_kernel
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int jx = slot / np;
+    const int p = p0 + (slot - jx * np);
+    const int cb = 8 * jx + xcd;
+    const int m = cb * lp.lpw + line;
+    const bool act = m < g.h;
+    const int nl = g.n0, M = lp.n;
+    int kb, k;
+    if (p < g.npair) decode_pair(g.P, p, kb, k);
+    else { kb = p - g.npair; k = sslot; }
+    const int K = p < g.npair ? 2 * g.w0 : g.w0;
+    cx<T>* buf = lds + line * line_lds_elems(M);
+    const cx<double>* __restrict__ ch = static_cast<const cx<double>*>(lp.chirp);
+    const cx<double>* __restrict__ bh = static_cast<const cx<double>*>(lp.bhat);
+    const cx<T>* __restrict__ twm = static_cast<const cx<T>*>(lp.twm);
+    auto wide = [](cx<T> a) { return mk((double)a.re, (double)a.im); };
+    auto narrow = [](cx<double> a) { return mk(T(a.re), T(a.im)); };
+    cx<T> v[kElemsPerThread];
+    const cx<T>* A = X + ((size_t)kb * g.h + (act ? m : 0)) * nl;
+    const cx<T>* B = X + ((size_t)k * g.h + (act ? m : 0)) * nl;
+#pragma unroll
+    for (int e = 0; e < kElemsPerThread; ++e) {
+        const int t = lt + e * tl;
+        const bool in = act && t < nl;
+        const int tc = t < nl ? t : nl - 1;
+        const cx<T> pr = cmulc(A[tc], B[tc]);
+        v[e] = in ? narrow(cmulc(ch[tc], wide(cconj(pr)))) : mk(T(0), T(0));
+    }
+    line_fft<-1, T, P>(v, buf, lp, lt, twt);
+#pragma unroll
+    for (int e = 0; e < kElemsPerThread; ++e) v[e] = narrow(cmul(wide(v[e]), bh[lt + e * tl]));
+    Dft<16, 1, T>::run(v);
+    __syncthreads();   // every thread is past the transform's LDS reads
+    // red[blk][wave of the line][16] in the line's buffer
+    const int nlo = (K + 16) / 16, nhi = (K + 15) / 16;
+#pragma unroll 1
+    for (int blk = 0; blk < nlo + nhi; ++blk) {
+        const int tb = blk < nlo ? 16 * blk : nl - K + 16 * (blk - nlo);
+        cx<T> s[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int kk = tb + ((r - tb) & 15);   // the slot's k (k = r mod 16)
+            s[r] = cmul(v[r], cconj(twm[(int)(((long long)lt * kk) & (M - 1))]));
+        }
+        wave_transpose_sum16(s, lane);
+        if ((lane & 3) == 0) buf[(blk * nwl + wl) * 16 + ((lane >> 2) & 15)] = s[0];
+    }
+    __syncthreads();
+    for (int o = lt; o < (nlo + nhi) * 16; o += tl) {
+        const int blk = o >> 4, r = o & 15;
+        const bool lo = blk < nlo;
+        const int tb = lo ? 16 * blk : nl - K + 16 * (blk - nlo);
+        const int kk = tb + ((r - tb) & 15);
+        if (!act || (lo ? kk > K : kk >= nl)) continue;
+        cx<T> z = buf[(blk * nwl) * 16 + r];
+        for (int w = 1; w < nwl; ++w) z = z + buf[(blk * nwl + w) * 16 + r];
+        const int d0 = lo ? kk : kk - nl;
+        Cl[((size_t)p * g.D0 + d0 + 2 * g.w0) * g.hp + m] = narrow(cmul(ch[kk], wide(cconj(z))));
+    }
+}
+
 // Block-wide sum of NV doubles per thread; result valid in lane 0 of wave 0
 // written to red[0..NV).
 template <int NV>
@@ -473,6 +559,27 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
     dim3 grid((ncb + 7) / 8 * 8 * (p1 - p0), 1, g.nb);
+    // Bluestein lines: one forward transform per product and the kept lags
+    // of the inverse only (needs waves of whole lines and the M-point twiddles)
+    if (!force_full && lp.chirp && lp.twm && lp.tl % 64 == 0) {
+        return with_line_plan(lp, [&](auto pl) -> hipError_t {
+            using PL = decltype(pl);
+            if constexpr (IsChirp<PL>::value) {
+                auto k = lagcol_chirp_kernel<T, PL>;
+                if (lds > 65536) {
+                    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)lds);
+                    if (e != hipSuccess) return e;
+                }
+                hipLaunchKernelGGL(k, grid, dim3(lp.tl * lp.lpw), lds, st, g, lp, p0, p1 - p0, sslot,
+                                   X, Cl, twt);
+                return hipGetLastError();
+            } else {
+                return hipErrorInvalidValue;   // lp.chirp always gives a Chirp plan
+            }
+        });
+    }
     return with_line_plan(lp, [&](auto pl) -> hipError_t {
         auto k = lagcol_kernel<T, decltype(pl)>;
         if (lds > 65536) {

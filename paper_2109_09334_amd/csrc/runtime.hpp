@@ -106,6 +106,7 @@ struct Twiddles {
     double* twp = nullptr;    // 2n doubles: cos, sin of +2 pi t / n
     void* chirp = nullptr;    // Bluestein lines: the plan's chirp and bhat
     void* bhat = nullptr;     // tables (cx<double>), null otherwise
+    void* twm = nullptr;      // Bluestein lines: e^(-2 pi i t / m), t < m (compute type)
 };
 
 // Per-stage HIP-event timers (enabled by sfft_profile): every stage of the
