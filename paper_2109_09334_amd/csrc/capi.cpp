@@ -475,7 +475,7 @@ static hipError_t lag_tables(Plan& pl, IoRef<const Tin> r, IoRef<const Tin> s, h
     if (!e) e = forward_fit<T, Tin>(pl, r, s, st);
     if (!e) {
         StageTimer t_(pl.prof, "lagcol", st);
-        e = launch_lagcol<T>(g, pl.lp0, 0, g.nprod, g.P, cxp<T>(w.X), cxp<T>(w.Cl), cxp<T>(pl.t0.tw), cxp<T>(pl.t0.twt), st);
+        e = launch_lagcol<T>(g, pl.lp0, 0, g.nprod, g.P, cxp<T>(w.X), cxp<T>(w.Cl), cxp<T>(pl.t0.tw), cxp<T>(pl.t0.twt), pl.t0.twp, st);
     }
     if (!e) {
         StageTimer t_(pl.prof, "lagrow", st);
@@ -580,7 +580,7 @@ static hipError_t refine(Plan& pl, double* coef, int gen, hipStream_t st) {
     jobs.nw[0] = 1;
     jobs.spec[0][0] = g.P + 1;
     if (!e) e = launch_colfwd<T>(g, pl.lp0, jobs, cxp<T>(w.Z), cxp<T>(w.X), cxp<T>(pl.t0.twt), st);
-    if (!e) e = launch_lagcol<T>(g, pl.lp0, g.npair, g.nprod, g.P + 1, cxp<T>(w.X), cxp<T>(w.Cl), cxp<T>(pl.t0.tw), cxp<T>(pl.t0.twt), st);
+    if (!e) e = launch_lagcol<T>(g, pl.lp0, g.npair, g.nprod, g.P + 1, cxp<T>(w.X), cxp<T>(w.Cl), cxp<T>(pl.t0.tw), cxp<T>(pl.t0.twt), pl.t0.twp, st);
     if (!e) e = launch_lagrow<T>(g, g.npair, g.nprod, cxp<T>(w.Cl), pl.t1.twp, w.omega, w.thetaD, st);
     if (!e) e = launch_lagfix(g, 1, w.ped, w.piR, w.piD, w.sig0, w.sig1, w.pw, dm, nullptr,
                               w.thetaD, nullptr, nullptr, w.evecD, st);

@@ -449,6 +449,120 @@ __global__ void __launch_bounds__(512) lagcol_chirp_kernel(Geom g, LinePlan lp, 
     }
 }
 
+// The same lags as a dense contraction on the FP32 matrix cores, for the
+// FP32 transforms of a Bluestein column (its length has no radix-16 split):
+// per column m, C(d0, p) = sum_l E(d0, l) P_p(l), E = e^(+2 pi i l d0 / N0),
+// for the products p of the call (conj(X_kb) X_k) and |d0| <= Kmax. As a real
+// product: rows 2 di + s (lag di = d0 + Kmax; s = 0 real, 1 imaginary part
+// of C), contraction index 2 l + c (c = 0 real, 1 imaginary part of P), so
+// the E block of (s, c) is [[Re E, -Im E], [Im E, Re E]]. Wave rb owns row
+// block rb (eight lags) and every 16-column block of products. N0 is taken
+// in chunks of 32 points: the chunk's column spectra and products are
+// staged in LDS (FP32), each lane steps its E(d0, l) through the chunk by
+// the FP64 recurrence E(l + 2) = E(l) e^(+2 pi i 2 d0 / N0) from a table
+// value, and the chunk's FP32 accumulators are added into FP64 totals (the
+// output register q of lane L holds row 4 (L / 16) + q, column L % 16, so a
+// lane ends with the real and imaginary parts of two lags).
+typedef float flt4 __attribute__((ext_vector_type(4)));
+constexpr int kDftChunk = 32;
+constexpr int kDftMaxSpec = 16;   // spectra a call reads (P + 2 at DK = 4)
+constexpr int kDftMaxProd = 64;   // products of a call (nprod = 35 at DK = 4)
+
+template <int NCB>
+__global__ void __launch_bounds__(512) lagcol_dft_kernel(Geom g, int p0, int np, int sslot,
+                                                          int nspec, int kmax,
+                                                          const cx<float>* __restrict__ X,
+                                                          cx<float>* __restrict__ Cl,
+                                                          const double* __restrict__ twp) {
+    __shared__ cx<float> xs[kDftMaxSpec][kDftChunk];
+    __shared__ cx<float> ps[kDftChunk][kDftMaxProd];
+    __shared__ unsigned char pkb[kDftMaxProd], pk[kDftMaxProd];
+    X = zoff(X, g.zs);
+    Cl = zoff(Cl, g.zs);
+    const int m = blockIdx.x, n0 = g.n0;
+    const int lane = threadIdx.x & 63, rb = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    constexpr int NPP = 16 * NCB;   // products padded to whole 16-column blocks
+    for (int t = threadIdx.x; t < np; t += blockDim.x) {
+        const int p = p0 + t;
+        int kb, k;
+        if (p < g.npair) decode_pair(g.P, p, kb, k);
+        else { kb = p - g.npair; k = sslot; }
+        pkb[t] = (unsigned char)kb;
+        pk[t] = (unsigned char)k;
+    }
+    // this lane's A row: lag d0 = (16 rb + lr) / 2 - kmax, part s = lr % 2;
+    // its contraction slots: point 2 j + lk / 2 of step j, part c = lk % 2
+    const int d0 = (16 * rb + lr) / 2 - kmax, sa = lr & 1, ca = lk & 1;
+    const int step = imod(2 * d0, n0);
+    const double sr = twp[2 * step], si = twp[2 * step + 1];   // e^(+2 pi i 2 d0 / N0)
+    double tot[NCB][4];
+#pragma unroll
+    for (int b = 0; b < NCB; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tot[b][q] = 0.0;
+    const cx<float>* xc = X + (size_t)m * n0;
+#pragma unroll 1
+    for (int l0 = 0; l0 < n0; l0 += kDftChunk) {
+        __syncthreads();   // the previous chunk's LDS reads are done
+        for (int t = threadIdx.x; t < nspec * kDftChunk; t += blockDim.x) {
+            const int sp = t / kDftChunk, l = l0 + t % kDftChunk;
+            xs[sp][t % kDftChunk] = l < n0 ? xc[(size_t)sp * g.h * n0 + l] : mk(0.0f, 0.0f);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < NPP * kDftChunk; t += blockDim.x) {
+            const int l = t / NPP, pp = t - l * NPP;
+            ps[l][pp] = pp < np ? cmulc(xs[pkb[pp]][l], xs[pk[pp]][l]) : mk(0.0f, 0.0f);
+        }
+        __syncthreads();
+        // E at this lane's first point of the chunk, l0 + lk / 2
+        // l0 < N0 <= 8192 and |d0| < 64: the product fits 32 bits
+        const int e0 = imod((l0 + (lk >> 1)) * d0 % n0, n0);
+        double er = twp[2 * e0], ei = twp[2 * e0 + 1];
+        // the lane's part (re / im) of P at column 16 b + lr, point 2 j + lk / 2
+        const float* pb = reinterpret_cast<const float*>(&ps[lk >> 1][lr]) + ca;
+        flt4 acc[NCB];
+#pragma unroll
+        for (int b = 0; b < NCB; ++b) acc[b] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < kDftChunk / 2; ++j) {
+            // A = [[Re E, -Im E], [Im E, Re E]] at (s, c)
+            const float a = (float)(sa == ca ? er : (sa ? ei : -ei));
+            float bv[NCB];
+#pragma unroll
+            for (int b = 0; b < NCB; ++b) bv[b] = pb[2 * (2 * j * kDftMaxProd + 16 * b)];
+#pragma unroll
+            for (int b = 0; b < NCB; ++b)
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[b], acc[b], 0, 0, 0);
+            const double nr = er * sr - ei * si;
+            ei = er * si + ei * sr;
+            er = nr;
+        }
+#pragma unroll
+        for (int b = 0; b < NCB; ++b) {
+            tot[b][0] += (double)acc[b].x;
+            tot[b][1] += (double)acc[b].y;
+            tot[b][2] += (double)acc[b].z;
+            tot[b][3] += (double)acc[b].w;
+        }
+    }
+    // rows 4 lk + q of row block rb: lag 8 rb + 2 lk (q = 0, 1) and + 1 (q = 2, 3)
+#pragma unroll
+    for (int b = 0; b < NCB; ++b) {
+        const int pp = 16 * b + lr;
+        if (pp >= np) continue;
+        const int p = p0 + pp;
+        const int K = p < g.npair ? 2 * g.w0 : g.w0;
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+            const int d = 8 * rb + 2 * lk + h2 - kmax;
+            if (d < -K || d > K) continue;
+            Cl[((size_t)p * g.D0 + d + 2 * g.w0) * g.hp + m] =
+                mk((float)tot[b][2 * h2], (float)tot[b][2 * h2 + 1]);
+        }
+    }
+}
+
 // Block-wide sum of NV doubles per thread; result valid in lane 0 of wave 0
 // written to red[0..NV).
 template <int NV>
@@ -532,7 +646,7 @@ __global__ void __launch_bounds__(256) lagrow_kernel(Geom g, int p0, const cx<T>
 template <typename T>
 hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int sslot,
                          const cx<T>* X, cx<T>* Cl, const cx<T>* tw, const cx<T>* twt,
-                         hipStream_t st) {
+                         const double* twp, hipStream_t st) {
     if (p1 <= p0) return hipSuccess;
     static const bool force_full = getenv("SFFT_LAGCOL_FULL") != nullptr;
     // (the pruned pass needs N0 = 16 x its threads per line: not a Bluestein line)
@@ -559,6 +673,25 @@ hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int 
     const size_t lds = (size_t)lp.lpw * line_lds_elems(lp.n) * sizeof(cx<T>);
     const int ncb = (g.h + lp.lpw - 1) / lp.lpw;
     dim3 grid((ncb + 7) / 8 * 8 * (p1 - p0), 1, g.nb);
+    // Bluestein lines, FP32, the build's products (all of them): the lags as a
+    // dense contraction on the matrix cores (row blocks of eight lags, up to
+    // 64 products in 16-column blocks); the refinement's few Theta products
+    // take the transform path below
+    if constexpr (sizeof(T) == 4) {
+        const int kmax = p0 == 0 ? 2 * g.w0 : g.w0;
+        const int nspec = std::max(g.P + 1, sslot + 1);
+        const int rbs = (2 * (2 * kmax + 1) + 15) / 16;
+        if (!force_full && p0 == 0 && lp.chirp && twp && rbs * 64 <= 512 &&
+            p1 - p0 <= kDftMaxProd && nspec <= kDftMaxSpec) {
+            const int ncb = (p1 - p0 + 15) / 16;
+            auto k = ncb == 1 ? lagcol_dft_kernel<1>
+                     : ncb == 2 ? lagcol_dft_kernel<2>
+                     : ncb == 3 ? lagcol_dft_kernel<3> : lagcol_dft_kernel<4>;
+            hipLaunchKernelGGL(k, dim3(g.h, 1, g.nb), dim3(64 * rbs), 0, st, g, p0, p1 - p0, sslot,
+                               nspec, kmax, X, Cl, twp);
+            return hipGetLastError();
+        }
+    }
     // Bluestein lines: one forward transform per product and the kept lags
     // of the inverse only (needs waves of whole lines and the M-point twiddles)
     if (!force_full && lp.chirp && lp.twm && lp.tl % 64 == 0) {
@@ -604,10 +737,10 @@ hipError_t launch_lagrow(const Geom& g, int p0, int p1, const cx<T>* Cl, const d
 
 template hipError_t launch_lagcol<float>(const Geom&, const LinePlan&, int, int, int,
                                          const cx<float>*, cx<float>*, const cx<float>*,
-                                         const cx<float>*, hipStream_t);
+                                         const cx<float>*, const double*, hipStream_t);
 template hipError_t launch_lagcol<double>(const Geom&, const LinePlan&, int, int, int,
                                           const cx<double>*, cx<double>*, const cx<double>*,
-                                          const cx<double>*, hipStream_t);
+                                          const cx<double>*, const double*, hipStream_t);
 template hipError_t launch_lagrow<float>(const Geom&, int, int, const cx<float>*, const double*,
                                          double*, double*, hipStream_t);
 template hipError_t launch_lagrow<double>(const Geom&, int, int, const cx<double>*, const double*,

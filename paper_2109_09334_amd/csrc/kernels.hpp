@@ -50,7 +50,7 @@ template <typename T>
 // tw: full twiddle table W_N0^t; twt: pass tables of the line plan.
 hipError_t launch_lagcol(const Geom& g, const LinePlan& lp, int p0, int p1, int sslot,
                          const cx<T>* X, cx<T>* Cl, const cx<T>* tw, const cx<T>* twt,
-                         hipStream_t st);
+                         const double* twp, hipStream_t st);
 template <typename T>
 hipError_t launch_lagrow(const Geom& g, int p0, int p1, const cx<T>* Cl, const double* twp,
                          double* omega, double* theta, hipStream_t st);
