@@ -121,7 +121,9 @@ __global__ void __launch_bounds__(512) colconv_kernel(Geom g, LinePlan lp, cx<T>
     if (act) {
         const T den0 = T(wts[0]);
         const T inv_n0 = T(1) / T(n0);
-#pragma unroll 1
+        // unrolled: v stays in registers (a run-time index would put it in
+        // scratch memory)
+#pragma unroll
         for (int e = 0; e < kElemsPerThread; ++e) {
             const int l = lt + e * lp.tl;
             if (!in_line<PL>(l, n0)) continue;
