@@ -487,14 +487,18 @@ __global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__
 // poll until the flag reaches gen, then acquire. The flags are cleared at
 // the start of each request (clear_flag_kernel) and every solve of the
 // request has the next generation, so no solve clears them itself.
-// Every workgroup of a pair runs on one XCD: workgroups are dealt to the 8
-// XCDs round robin and each XCD starts its own in order, so workgroup i
-// (XCD i mod 8, j = i / 8 its place there) takes pair (i mod 8) + 8 (j / 2T)
-// and order x = j mod 2T within it: forward block x for x < T, backward
-// block 2T-1-x after. Every block a workgroup waits for is then earlier on
-// the same XCD, already started, whatever else runs on the other XCDs; the
-// flags stay in one L2. Each poll is bounded: past the bound the block sets
-// kFlagStall and goes on (its result is then NaN).
+// Placement. A pair's 2T tasks x (forward block x for x < T, then backward
+// block 2T-1-x) each wait only for earlier tasks. Workgroups are dealt to
+// the 8 XCDs round robin and each XCD starts its own in order; workgroup i
+// is XCD i mod 8, place j = i / 8 there. Batches: every task of a pair on
+// one XCD (pair (i mod 8) + 8 (j / 2T), task x = j mod 2T), its flags in one
+// L2. One pair: its tasks in 8 contiguous chunks of cs = ceil(2T / 8), chunk
+// c on XCD c (task x = c cs + j), which spreads the hand-offs' cache
+// maintenance over the XCDs. Either way every task a workgroup waits for is
+// earlier on the same XCD (already started) or on a lower XCD, whose tasks
+// wait only on earlier or lower ones: whatever else runs on the GPU, no wait
+// can be on a workgroup that cannot start. Each poll is bounded: past the
+// bound the block sets kFlagStall and goes on (its result is then NaN).
 // Waits (thread 0, at most `spin` polls) until *f reaches gen, then makes
 // the producer's writes visible to the whole workgroup.
 __device__ __forceinline__ void wait_flag(const int* f, int gen, int spin, int* flag) {
@@ -523,8 +527,17 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
     __shared__ double vsh[NBK];
     const int T = (n + NBK - 1) / NBK;
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    const int pair = xcd + 8 * (j / (2 * T)), x = j % (2 * T);
-    if (pair >= npairs) return;   // uniform over the workgroup, before any barrier
+    int pair, x;
+    if (npairs == 1) {
+        const int cs = (2 * T + 7) / 8;
+        pair = 0;
+        x = xcd * cs + j;
+        if (j >= cs || x >= 2 * T) return;   // uniform over the workgroup, before any barrier
+    } else {
+        pair = xcd + 8 * (j / (2 * T));
+        x = j % (2 * T);
+        if (pair >= npairs) return;
+    }
     const long long zo = (long long)pair * zstride;
     auto at = [zo](auto* p) {
         return reinterpret_cast<decltype(p)>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)zo);
@@ -635,9 +648,9 @@ hipError_t launch_chol_solve(const Geom& g, int n, const double* L, const double
     // publishes, with a short bound: each wait gives up, every block exits
     const int wait_gen = stall_test ? 0x7fffffff : gen;
     const int spin = stall_test ? kStallTestSpin : kSolveSpin;
-    // 2T workgroups per pair, the pairs dealt to the XCDs (see the kernel)
-    const int rounds = (g.nb + 7) / 8;
-    hipLaunchKernelGGL(trsv_flow_kernel, dim3(8 * 2 * T * rounds), dim3(256), 0, st, n, L, dinv, dsc,
+    // placement: see the kernel
+    const int wgs = g.nb == 1 ? 8 * ((2 * T + 7) / 8) : 8 * 2 * T * ((g.nb + 7) / 8);
+    hipLaunchKernelGGL(trsv_flow_kernel, dim3(wgs), dim3(256), 0, st, n, L, dinv, dsc,
                        rhs, coef, accumulate, flag, tsv, tflag, gen, wait_gen, spin, g.nb, g.zs);
     return hipGetLastError();
 }
