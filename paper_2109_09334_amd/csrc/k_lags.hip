@@ -195,11 +195,12 @@ __device__ __forceinline__ int lag_twiddle_index(int n0, int j, int tb, int r) {
     return idx;
 }
 
-// NB > 0: the Omega lags span NB blocks of 16 and the thread's 16 NB
-// twiddles (FP32) or twiddle-table indices (FP64) are formed once and kept in
-// registers (Theta's lags lie in the same range at the same slot residues,
-// so they select from them); NB = 0: indices are formed per product and
-// block.
+// NB > 0: the Omega lags span NB blocks of 16 and the thread's twiddles are
+// formed once and kept in registers: FP32, block 0's 16 twiddles and the
+// factor that carries them to block 1; FP64, the 16 NB table indices
+// (Theta's lags lie in the same range at the same slot residues, so they
+// take the Omega block's twiddle); NB = 0: indices are formed per product
+// and block.
 template <typename T, int NB>
 __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, int ir_only,
                                                            int sslot, int pchunk,
@@ -232,15 +233,17 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
     const bool act = m < g.h;
     const int n0 = g.n0;
     const int KO = 2 * g.w0, nblk = (2 * KO + 16) / 16;   // lag blocks of Omega (Theta uses fewer)
-    // FP32: the conjugated twiddles of the NB Omega blocks stay in registers
-    // (one workgroup per CU leaves room); FP64: their table indices do.
+    // FP32: the conjugated twiddles of Omega block 0 stay in registers. Slot
+    // r of block b carries the lag of block 0's slot r plus 16 b, so block
+    // 1's twiddles are block 0's times the one factor e^(+2 pi i 16 j / N0)
+    // (16 j < N0), which is all that is kept for it. FP64: the NB blocks'
+    // table indices stay in registers.
     int twi[(NB > 0 && !kTwReg) ? NB : 1][16];
-    cx<T> twv[kTwReg ? NB : 1][16];
+    cx<T> tw0[16], tstep = mk(T(1), T(0));
     if constexpr (kTwReg) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) twv[b][r] = cconj(tw[lag_twiddle_index(n0, j, -KO + 16 * b, r)]);
+        for (int r = 0; r < 16; ++r) tw0[r] = cconj(tw[lag_twiddle_index(n0, j, -KO, r)]);
+        if constexpr (NB == 2) tstep = cconj(tw[16 * j]);
     } else if constexpr (NB > 0) {
 #pragma unroll
         for (int b = 0; b < NB; ++b)
@@ -280,37 +283,36 @@ __global__ void __launch_bounds__(512) lagcol_tail_kernel(Geom g, LinePlan lp, i
                     for (int q = 0; q < 16; ++q) v[q] = mk(T(0), T(0));
                 }
                 if constexpr (kTwReg) {
-                    // Omega blocks use their own twiddles; Theta's slots select
-                    // the Omega block their lag lies in
-                    auto blocks = [&](auto theta_c) {
-                        constexpr bool TH = decltype(theta_c)::value;
+                    // NB <= 2 gives Omega NB blocks and Theta (|t| <= w0 < 8)
+                    // one, whose slot r lies in Omega block (t + KO) / 16 at
+                    // the same residue (uniform over the wave)
+                    cx<T> s[16];
 #pragma unroll
-                        for (int blk = 0; blk < NB; ++blk) {
-                            if (16 * blk > 2 * K) break;
-                            cx<T> s[16];
+                    for (int r = 0; r < 16; ++r) s[r] = cmul(v[r], tw0[r]);
+                    auto store = [&](cx<T>* x, int blk) {
+                        wave_transpose_sum16(x, lane);
+                        if ((lane & 3) == 0)
+                            red[(((size_t)(kk - k0) * nblk + blk) * nwv + wv) * 16 + ((lane >> 2) & 15)] = x[0];
+                    };
+                    if constexpr (NB == 2) {
+                        if (theta) {
+                            const int tb = -K, mres = tb & 15;
 #pragma unroll
                             for (int r = 0; r < 16; ++r) {
-                                cx<T> w = twv[blk][r];
-                                if constexpr (TH) {
-                                    const int tb = -K + 16 * blk, mres = tb & 15;
-                                    const int t = tb - mres + r + (r < mres ? 16 : 0);
-                                    const int ob = (t + KO) >> 4;
-                                    w = twv[0][r];
-#pragma unroll
-                                    for (int b = 1; b < NB; ++b)
-                                        if (b == ob) w = twv[b][r];
-                                }
-                                s[r] = cmul(v[r], w);
+                                const int t = tb - mres + r + (r < mres ? 16 : 0);
+                                if (t + KO >= 16) s[r] = cmul(s[r], tstep);
                             }
-                            wave_transpose_sum16(s, lane);
-                            if ((lane & 3) == 0)
-                                red[(((size_t)(kk - k0) * nblk + blk) * nwv + wv) * 16 + ((lane >> 2) & 15)] = s[0];
+                            store(s, 0);
+                        } else {
+                            cx<T> s1[16];
+#pragma unroll
+                            for (int r = 0; r < 16; ++r) s1[r] = cmul(s[r], tstep);
+                            store(s, 0);
+                            store(s1, 1);
                         }
-                    };
-                    if (theta)
-                        blocks(std::true_type{});
-                    else
-                        blocks(std::false_type{});
+                    } else {
+                        store(s, 0);
+                    }
                     continue;
                 }
                 for (int blk = 0; 16 * blk <= 2 * K; ++blk) {
