@@ -339,11 +339,12 @@ __global__ void __launch_bounds__(256) stencil_reg_kernel(Geom g, const cx<T>* _
 #pragma unroll
                     for (int i = NI - 1; i >= 0; --i)
                         poly = mk(fmat(poly.re, c, kt[i].re), fmat(poly.im, c, kt[i].im));
-                    // the tap's term first, so that each tap rounds once at
-                    // the accumulator's magnitude (|Z_S|, far above the result)
-                    const cx<T> t = mk(fmat(poly.re, z[s].re, -poly.im * z[s].im),
-                                       fmat(poly.re, z[s].im, poly.im * z[s].re));
-                    acc[o] = acc[o] - t;
+                    // two FMAs per component into the accumulator: two
+                    // roundings per tap at its magnitude (|Z_S|, far above
+                    // the result) against one for forming the tap's term
+                    // first, for 4 instead of 6 instructions per tap
+                    acc[o].re = fmat(-poly.re, z[s].re, fmat(poly.im, z[s].im, acc[o].re));
+                    acc[o].im = fmat(-poly.re, z[s].im, fmat(-poly.im, z[s].re, acc[o].im));
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
