@@ -175,7 +175,8 @@ __device__ __forceinline__ dbl4 mfma16(const double (*P)[NBK + 1], int pr,
 //      i; the pivot and the column below it are broadcast by readlane): the
 //      16 dependent steps need no barrier;
 //  (2) every row below the block in D and every row of A is solved against
-//      L_jj, one row per thread (y_j = (a_j - sum_(k<j) y_k L_jk) / L_jj);
+//      L_jj, one row per thread (y_j = (a_j - sum_(k<j) y_k L_jk) / L_jj,
+//      the terms subtracted as each y_k is formed);
 //  (3) the 16 x 16 blocks right of the column block take the rank-16 update
 //      (D_IJ -= L_Ij L_Jj^T for J <= I, A_IJ -= Y_I L_Jj^T) on the FP64
 //      matrix cores, one block per wave at a time.
@@ -194,18 +195,31 @@ __device__ __forceinline__ void factor_panel(double (*D)[NBK + 1], double (*A)[N
 #pragma unroll
             for (int c = 0; c < 16; ++c) r[c] = D[c0 + li][c0 + c];
             bool bad = false, nonfin = false;
+            // dn: in lane j, the pivot of step j once the steps before it are
+            // applied. Lane j + 1 forms it from its own scaled entry, so the
+            // dependent chain from pivot to pivot is one broadcast, the
+            // reciprocal square root, the scale and one FMA; the broadcasts
+            // of the column for the other updates run beside it.
+            double dn = r[0];
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                double piv = bcast(r[j], j);
-                if (!(piv > 0.0) || !isfinite(piv)) {
+                const double pv = bcast(dn, j);
+                const bool ok = pv > 0.0 && isfinite(pv);   // uniform
+                if (!ok) {
                     bad = true;
-                    nonfin |= !isfinite(piv);
-                    piv = 1.0;
+                    nonfin |= !isfinite(pv);
                 }
-                const double inv = rsqrt(piv), ljj = piv * inv;
-                r[j] = li > j ? r[j] * inv : (li == j ? ljj : 0.0);
+                // hardware estimate and one Newton step with the cubic term,
+                // y (1 + e/2 + 3e^2/8), e = 1 - x y^2 (a positive finite
+                // pivot needs no special cases); a bad pivot is taken as 1
+                const double y0 = __builtin_amdgcn_rsq(pv);
+                const double e = fma(-(pv * y0), y0, 1.0);
+                const double inv = ok ? fma(y0 * e, fma(e, 0.375, 0.5), y0) : 1.0;
+                const double lj = r[j] * inv;
+                if (j < 15) dn = fma(-lj, lj, r[j + 1]);
+                r[j] = li > j ? lj : (li == j ? (ok ? pv : 1.0) * inv : 0.0);
 #pragma unroll
-                for (int kc = j + 1; kc < 16; ++kc) r[kc] -= r[j] * bcast(r[j], kc);
+                for (int kc = j + 1; kc < 16; ++kc) r[kc] = fma(-r[j], bcast(r[j], kc), r[kc]);
             }
             if (lane < 16) {
 #pragma unroll
@@ -221,11 +235,15 @@ __device__ __forceinline__ void factor_panel(double (*D)[NBK + 1], double (*A)[N
             double* row = t < nd ? D[c0 + 16 + t] : A[t - nd];
             double y[16];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                double v = row[c0 + j];
+            for (int j = 0; j < 16; ++j) y[j] = row[c0 + j];
+            // right-looking: y_j is final once scaled, then leaves its term
+            // in every later entry, so the dependent chain is one product
+            // and one FMA per column
 #pragma unroll
-                for (int kc = 0; kc < j; ++kc) v -= y[kc] * D[c0 + j][c0 + kc];
-                y[j] = v * rdiag[j];
+            for (int j = 0; j < 16; ++j) {
+                y[j] *= rdiag[j];
+#pragma unroll
+                for (int kc = j + 1; kc < 16; ++kc) y[kc] = fma(-y[j], D[c0 + kc][c0 + j], y[kc]);
             }
 #pragma unroll
             for (int j = 0; j < 16; ++j) row[c0 + j] = y[j];
