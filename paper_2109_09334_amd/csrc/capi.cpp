@@ -347,7 +347,7 @@ int create_plan(sfft_ctx* ctx, const sfft_params* p, std::unique_ptr<Plan>& out,
     all.nb = cap;
     // (on init_stream, ahead of the plan's first use there; on the null
     // stream, waited for, when none is given)
-    if (launch_clear_flag(all, pl->ws.flag, pl->ws.tflag, tflag_len(all), init_stream) != hipSuccess ||
+    if (launch_clear_flag(all, pl->ws.flag, pl->ws.tsv, init_stream) != hipSuccess ||
         launch_polysum(all, poly_degree(all), pl->ws.sig0, pl->ws.sig1, pl->ws.pw, init_stream) !=
             hipSuccess ||
         (!init_stream && hipStreamSynchronize(nullptr) != hipSuccess)) {
@@ -536,7 +536,7 @@ static hipError_t factor_solve(Plan& pl, const double* G, const double* h, doubl
     }
     if (!e) {
         StageTimer t_(pl.prof, "trsv", st);
-        e = launch_chol_solve(pl.g, n, w.L, w.dinv, w.dsc, h, coef, 0, w.flag, w.tsv, w.tflag, 1,
+        e = launch_chol_solve(pl.g, n, w.L, w.dinv, w.dsc, h, coef, 0, w.flag, w.tsv, 1,
                               pl.stall_test, st);
     }
     return e;
@@ -585,7 +585,7 @@ static hipError_t refine(Plan& pl, double* coef, int gen, hipStream_t st) {
     if (!e) e = launch_lagfix(g, 1, w.ped, w.piR, w.piD, w.sig0, w.sig1, w.pw, dm, nullptr,
                               w.thetaD, nullptr, nullptr, w.evecD, st);
     if (!e) e = launch_gather(g, w.omega, w.thetaD, w.lam, w.cmat, w.evecD, nullptr, w.rhs, 1, st);
-    if (!e) e = launch_chol_solve(g, g.nu, w.L, w.dinv, w.dsc, w.rhs, coef, 1, w.flag, w.tsv, w.tflag,
+    if (!e) e = launch_chol_solve(g, g.nu, w.L, w.dinv, w.dsc, w.rhs, coef, 1, w.flag, w.tsv,
                                   gen, pl.stall_test, st);
     return e;
 }
@@ -608,7 +608,7 @@ static int run_build_t(Plan& pl, const void* r, const void* s, double* G, double
 template <typename T, typename Tin>
 static int run_solve_t(Plan& pl, const double* G, const double* h, const void* r, const void* s,
                        double* coef, hipStream_t st) {
-    hipError_t e = launch_clear_flag(pl.g, pl.ws.flag, pl.ws.tflag, tflag_len(pl.g), st);
+    hipError_t e = launch_clear_flag(pl.g, pl.ws.flag, pl.ws.tsv, st);
     if (!e) e = factor_solve(pl, G, h, coef, st);
     if (!e && pl.p.precision == SFFT_MIXED && r && s) {
         e = poly_tables<Tin>(pl, (const Tin*)r, (const Tin*)s, st);
@@ -645,7 +645,7 @@ static hipError_t all_path(Plan& pl, IoRef<const Tin> rf, IoRef<const Tin> sf, I
                            IoRef<const Tin> s, IoRef<double> coef, IoRef<Tin> d, bool same_pair,
                            hipStream_t st) {
     Workspace& w = pl.ws;
-    hipError_t e = launch_clear_flag(pl.g, w.flag, w.tflag, tflag_len(pl.g), st);
+    hipError_t e = launch_clear_flag(pl.g, w.flag, w.tsv, st);
     if (!e) e = build<T, Tin>(pl, rf, sf, w.G, w.h, st);
     if (!e) e = factor_solve(pl, w.G, w.h, w.coef, st);
     for (int it = 0; !e && pl.p.precision == SFFT_MIXED && it < refine_steps(); ++it)

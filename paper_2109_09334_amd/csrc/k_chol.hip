@@ -19,13 +19,24 @@ constexpr int kFlagNonFinite = 2;
 constexpr int kFlagStall = 4;          // a bounded wait ran out (never expected)
 constexpr int kSolveSpin = 1 << 22;    // bound of every poll loop
 constexpr int kStallTestSpin = 64;     // the bound under the give-up test
+// An empty entry of the triangular solves' result buffers: a signalling NaN,
+// which no arithmetic result equals (results are never signalling NaNs)
+constexpr unsigned long long kTsvEmpty = 0x7FF4000000005EEDull;
 
-// A request's start: status flag and the solves' block flags cleared.
-__global__ void clear_flag_kernel(int* flag, int* tflag, int m, long long zs) {
+// The result buffer (2 n entries: forward, then backward) of the solve of
+// generation gen: two buffers alternate.
+__host__ __device__ __forceinline__ unsigned long long* tsv_buffer(double* tsv, int n, int gen) {
+    return reinterpret_cast<unsigned long long*>(tsv) + (size_t)(gen & 1) * 2 * n;
+}
+
+// A request's start: status flag cleared, and the result buffer of its first
+// solve (generation 1) emptied.
+__global__ void clear_flag_kernel(int* flag, double* tsv, int n, long long zs) {
     flag = zoff(flag, zs);
-    tflag = zoff(tflag, zs);
+    tsv = zoff(tsv, zs);
     if (threadIdx.x == 0) *flag = 0;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) tflag[i] = 0;
+    unsigned long long* b = tsv_buffer(tsv, n, 1);
+    for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) b[i] = kTsvEmpty;
 }
 
 // Jacobi scaling, one block per row i: L_ij = d_i G_ij d_j (j <= i) with
@@ -500,11 +511,17 @@ __global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__
 // workgroup takes its dependency blocks in a fixed order (forward C = 0, 1,
 // ..., backward y_B first, then C = T-1, T-2, ...), so the sums do not depend
 // on timing; while it waits for block C it already holds that tile's row
-// slices and its W in registers. A block's result goes to tsv, then its
-// completion flag is set to the solve's generation gen (release); readers
-// poll until the flag reaches gen, then acquire. The flags are cleared at
-// the start of each request (clear_flag_kernel) and every solve of the
-// request has the next generation, so no solve clears them itself.
+// slices and its W in registers.
+// Hand-off. The results are the flags: every entry of the solve's result
+// buffer starts empty (kTsvEmpty), the producing thread stores its value
+// with a relaxed device-scope atomic, and each reading thread polls its own
+// entries with relaxed device-scope atomic loads until they are not empty.
+// Each entry is published and read on its own, so per-location coherence is
+// all the hand-off needs: no fences (an agent-scope release or acquire
+// writes back or invalidates the whole L2 of an XCD). The buffers of
+// generations gen and gen + 1 alternate; a solve empties the next
+// generation's buffer (its own blocks' entries) while it runs, and
+// clear_flag_kernel empties generation 1's at the request's start.
 // Placement. A pair's 2T tasks x (forward block x for x < T, then backward
 // block 2T-1-x) each wait only for earlier tasks. Workgroups are dealt to
 // the 8 XCDs round robin and each XCD starts its own in order; workgroup i
@@ -517,21 +534,20 @@ __global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__
 // wait only on earlier or lower ones: whatever else runs on the GPU, no wait
 // can be on a workgroup that cannot start. Each poll is bounded: past the
 // bound the block sets kFlagStall and goes on (its result is then NaN).
-// Waits (thread 0, at most `spin` polls) until *f reaches gen, then makes
-// the producer's writes visible to the whole workgroup.
-__device__ __forceinline__ void wait_flag(const int* f, int gen, int spin, int* flag) {
-    if (threadIdx.x == 0) {
-        int spins = 0;
-        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins >= spin) {
-                atomicOr(flag, kFlagStall);
-                break;
-            }
+// The value of result entry v once it is published (at most `spin` polls;
+// past that kFlagStall and NaN).
+__device__ __forceinline__ double wait_value(const unsigned long long* v, int spin, int* flag) {
+    unsigned long long u = __hip_atomic_load(v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int spins = 0;
+    while (u == kTsvEmpty) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins >= spin) {
+            atomicOr(flag, kFlagStall);
+            break;
         }
+        u = __hip_atomic_load(v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return __builtin_bit_cast(double, u);
 }
 
 __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __restrict__ L,
@@ -539,9 +555,9 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
                                                          const double* __restrict__ dsc,
                                                          const double* __restrict__ b,
                                                          double* __restrict__ coef, int accumulate,
-                                                         int* flag, double* tsv, int* tflag,
-                                                         int gen, int wait_gen, int spin,
-                                                         int npairs, long long zstride) {
+                                                         int* flag, double* tsv, int gen,
+                                                         int publish, int spin, int npairs,
+                                                         long long zstride) {
     __shared__ double vsh[NBK];
     const int T = (n + NBK - 1) / NBK;
     const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
@@ -567,15 +583,13 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
     coef = at(coef);
     flag = at(flag);
     tsv = at(tsv);
-    tflag = at(tflag);
     const bool fwd = x < T;
     const int B = fwd ? x : 2 * T - 1 - x;
     const int r0 = B * NBK, nb = min(NBK, n - r0);
     const int i = threadIdx.x >> 2, p = threadIdx.x & 3;   // row, quarter of the columns
-    double* ys = tsv;
-    double* zs = tsv + n;
-    int* fdone = tflag;       // forward block C done
-    int* bdone = tflag + T;   // backward block C done
+    unsigned long long* res = tsv_buffer(tsv, n, gen);      // y: [0, n), z: [n, 2n)
+    // this block's entries of the next generation's buffer emptied
+    if (p == 0 && i < nb) tsv_buffer(tsv, n, gen + 1)[(fwd ? 0 : n) + r0 + i] = kTsvEmpty;
     // this block's inverse (row i, columns 16 p ..), loaded while waiting
     const double* W = dinv + (size_t)B * 2 * NBK * NBK + (fwd ? 0 : NBK * NBK);
     double w[16];
@@ -590,10 +604,9 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
         const double* row = L + (size_t)(r0 + min(i, nb - 1)) * n;
 #pragma unroll
         for (int q = 0; q < 16; ++q) m[q] = (i < nb && c0 + q < n) ? row[c0 + q] : 0.0;
-        wait_flag(fwd ? fdone + C : bdone + C, wait_gen, spin, flag);
         if (threadIdx.x < NBK) {
             const int cc = C * NBK + threadIdx.x;
-            vsh[threadIdx.x] = cc < n ? (fwd ? ys : zs)[cc] : 0.0;
+            vsh[threadIdx.x] = cc < n ? wait_value(res + (fwd ? 0 : n) + cc, spin, flag) : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -602,9 +615,9 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
     }
     acc += __shfl_xor(acc, 1, 64);
     acc += __shfl_xor(acc, 2, 64);
-    if (!fwd) wait_flag(fdone + B, wait_gen, spin, flag);   // y_B
     if (p == 0) {
-        const double rhs = i < nb ? (fwd ? dsc[r0 + i] * b[r0 + i] : ys[r0 + i]) : 0.0;
+        const double rhs = i < nb ? (fwd ? dsc[r0 + i] * b[r0 + i] : wait_value(res + r0 + i, spin, flag))
+                                  : 0.0;
         vsh[i] = i < nb ? rhs - acc : 0.0;
     }
     __syncthreads();
@@ -614,23 +627,19 @@ __global__ void __launch_bounds__(256) trsv_flow_kernel(int n, const double* __r
     y += __shfl_xor(y, 1, 64);
     y += __shfl_xor(y, 2, 64);
     if (p == 0 && i < nb) {
-        if (fwd) {
-            ys[r0 + i] = y;
-        } else {
-            zs[r0 + i] = y;
+        if (publish)
+            __hip_atomic_store(res + (fwd ? 0 : n) + r0 + i, __builtin_bit_cast(unsigned long long, y),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!fwd) {
             const bool bad = *flag != 0;
             const double z = bad ? __builtin_nan("") : dsc[r0 + i] * y;
             coef[r0 + i] = accumulate ? coef[r0 + i] + z : z;
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0)
-        __hip_atomic_store(fwd ? fdone + B : bdone + B, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-hipError_t launch_clear_flag(const Geom& g, int* flag, int* tflag, int m, hipStream_t st) {
-    hipLaunchKernelGGL(clear_flag_kernel, dim3(1, 1, g.nb), dim3(64), 0, st, flag, tflag, m, g.zs);
+hipError_t launch_clear_flag(const Geom& g, int* flag, double* tsv, hipStream_t st) {
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1, 1, g.nb), dim3(256), 0, st, flag, tsv, g.nu, g.zs);
     return hipGetLastError();
 }
 
@@ -660,16 +669,15 @@ hipError_t launch_cholesky(const Geom& g, int n, double* L, double* dfac, double
 hipError_t launch_chol_solve(const Geom& g, int n, const double* L, const double* dinv,
                              const double* dsc,
                              const double* rhs, double* coef, int accumulate, int* flag,
-                             double* tsv, int* tflag, int gen, int stall_test, hipStream_t st) {
+                             double* tsv, int gen, int stall_test, hipStream_t st) {
     const int T = (n + NBK - 1) / NBK;
-    // under the give-up test every wait is for a generation no block
-    // publishes, with a short bound: each wait gives up, every block exits
-    const int wait_gen = stall_test ? 0x7fffffff : gen;
+    // under the give-up test no block publishes its result, and the bound is
+    // short: each wait gives up, every block exits
     const int spin = stall_test ? kStallTestSpin : kSolveSpin;
     // placement: see the kernel
     const int wgs = g.nb == 1 ? 8 * ((2 * T + 7) / 8) : 8 * 2 * T * ((g.nb + 7) / 8);
     hipLaunchKernelGGL(trsv_flow_kernel, dim3(wgs), dim3(256), 0, st, n, L, dinv, dsc,
-                       rhs, coef, accumulate, flag, tsv, tflag, gen, wait_gen, spin, g.nb, g.zs);
+                       rhs, coef, accumulate, flag, tsv, gen, stall_test ? 0 : 1, spin, g.nb, g.zs);
     return hipGetLastError();
 }
 

@@ -92,19 +92,21 @@ hipError_t launch_jacobi(const Geom& g, int n, const double* G, const double* h,
 // with the factor in its lower and its transpose in its upper triangle.
 hipError_t launch_cholesky(const Geom& g, int n, double* L, double* dfac, double* dinv, int* flag,
                            hipStream_t st);
-// coef (+)= solution of G c = rhs (rhs is read only). tsv: scratch of 2 n
-// doubles, tflag: of 2 ceil(n/64) ints. flag gains kFlagStall if a block
-// of the solve waited past its bound (a broken dependency, never expected).
-// gen: this solve's generation within the request (1, 2, ...): the block
-// flags in tflag are cleared by launch_clear_flag at the request's start.
-// stall_test: every block-to-block wait waits for a generation that is never
-// published, with a short bound (tests the give-up path from the host).
+// coef (+)= solution of G c = rhs (rhs is read only). tsv: scratch of 4 n
+// doubles, the block results of two consecutive solves. flag gains
+// kFlagStall if a block of the solve waited past its bound (a broken
+// dependency, never expected). gen: this solve's generation within the
+// request (1, 2, ...); launch_clear_flag at the request's start prepares
+// generation 1, and each solve the next one.
+// stall_test: no block publishes its result and every block-to-block wait
+// has a short bound (tests the give-up path from the host).
 hipError_t launch_chol_solve(const Geom& g, int n, const double* L, const double* dinv,
                              const double* dsc,
                              const double* rhs, double* coef, int accumulate, int* flag,
-                             double* tsv, int* tflag, int gen, int stall_test, hipStream_t st);
-// Status flag and the m solve block flags of a request cleared.
-hipError_t launch_clear_flag(const Geom& g, int* flag, int* tflag, int m, hipStream_t st);
+                             double* tsv, int gen, int stall_test, hipStream_t st);
+// A request's start: status flag cleared, the first solve's results emptied
+// (n = g.nu).
+hipError_t launch_clear_flag(const Geom& g, int* flag, double* tsv, hipStream_t st);
 // The caller buffers of the pairs of a batch: p[z] = r_fit, s_fit, r, s,
 // coef, d of pair z (slots kIo*).
 constexpr int kMaxBatch = 16;

@@ -47,13 +47,10 @@ struct Workspace {
     double *G, *h, *L, *dsc, *rhs, *coef, *dfac, *dinv;
     int* flag;
     void** io;                 // caller buffers of the request in flight (graph replays)
-    double* tsv;               // triangular solves: forward and backward block results
-    int* tflag;                // their per-block completion flags
+    double* tsv;               // triangular solves' block results, two generations
 };
 
 inline int poly_degree(const Geom& g) { return g.dk > g.db ? g.dk : g.db; }
-// Block flags of the triangular solves: forward and backward per 64 rows.
-inline int tflag_len(const Geom& g) { return 2 * ((g.nu + 63) / 64); }
 
 inline size_t carve(Workspace& w, const Geom& g, size_t cxb, size_t reb, char* base) {
     Carver c;
@@ -94,8 +91,7 @@ inline size_t carve(Workspace& w, const Geom& g, size_t cxb, size_t reb, char* b
     w.dinv = c.take<double>(base, (size_t)((g.nu + 63) / 64) * 2 * 64 * 64);
     w.flag = c.take<int>(base, 64);
     w.io = c.take<void*>(base, kIoSlots);
-    w.tsv = c.take<double>(base, 2 * (size_t)g.nu);
-    w.tflag = c.take<int>(base, tflag_len(g));
+    w.tsv = c.take<double>(base, 4 * (size_t)g.nu);
     return c.off + 256;
 }
 
