@@ -46,18 +46,23 @@ __global__ void __launch_bounds__(512) rowfwd_kernel(Geom g, LinePlan lp, RowSou
         // the thread index through an opaque zero: addresses are formed per
         // packed pair instead of held in registers across the loop
         const int lt = lt0 + opaque_zero();
-        // both rows loaded unconditionally (pb is a valid row when the pair
-        // has no second source), then the weights applied (a Bluestein line's
-        // padding, t >= n1, loads a valid pixel and is zeroed after)
+        // the pair's rows loaded, then the weights applied (a Bluestein
+        // line's padding, t >= n1, loads a valid pixel and is zeroed after);
+        // two weights of one image row, or a pair without a second source,
+        // load the row once (uniform over the launch)
+        const bool one_row = !src.rowpair && (!hasb || src.img[ia] == src.img[ib]);
         const Tin* pa = (src.img[ia] ? img1 : img0) + (size_t)xa * n1;
         const Tin* pb = (hasb && src.img[ib] ? img1 : img0) + (size_t)xb * n1;
         Tin la[kElemsPerThread], lb[kElemsPerThread];
         if (act) {
 #pragma unroll
-            for (int e = 0; e < kElemsPerThread; ++e) {
-                const int t = pad_index<PL>(lt + e * lp.tl, n1);
-                la[e] = pa[t];
-                lb[e] = pb[t];
+            for (int e = 0; e < kElemsPerThread; ++e) la[e] = pa[pad_index<PL>(lt + e * lp.tl, n1)];
+            if (one_row) {
+#pragma unroll
+                for (int e = 0; e < kElemsPerThread; ++e) lb[e] = la[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < kElemsPerThread; ++e) lb[e] = pb[pad_index<PL>(lt + e * lp.tl, n1)];
             }
         }
         cx<T> v[kElemsPerThread];
