@@ -480,13 +480,18 @@ def main():
     # arrivals at 0.5 / 0.8 / 0.95 of it, both forms
     stream = None
     if not args.no_stream:
+        # the closed-loop engine's idle workspaces (up to its budget) are
+        # freed for the stream's engine, and a fresh one serves C4 below
+        srv.close()
+        srv = sf.Context(0, budget)
+        srv.engine_config(args.slots, args.max_batch)
         stream = {}
         for name, prec in (("mixed", sf.MIXED), ("fp64", sf.FP64)):
             if name == "fp64" and args.no_fp64:
                 continue
-            # an untimed burst first: it creates the form's plans and graphs
-            # (and evicts the other form's), which the timed burst then reuses
-            mix_saturated(prec, max(1, args.mix_batch // 4))
+            # the same burst untimed first: it creates the form's plans and
+            # graphs (and evicts the other form's), which the timed one reuses
+            mix_saturated(prec, args.mix_batch)
             sat = mix_saturated(prec, args.mix_batch)
             pts = {}
             for frac in (0.5, 0.8, 0.95):

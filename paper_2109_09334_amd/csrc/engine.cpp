@@ -106,10 +106,25 @@ static int pow2_at_least(int n) {
     return c;
 }
 
+void Engine::make_idle(std::unique_ptr<Plan> pl) {
+    pl->idle_since = ++idle_tick_;
+    auto key = key_of(&pl->p);
+    idle_.emplace(key, std::move(pl));
+}
+
+std::multimap<PlanKey, std::unique_ptr<Plan>>::iterator Engine::eviction_victim() {
+    auto v = idle_.begin();
+    for (auto it = idle_.begin(); it != idle_.end(); ++it)
+        if (it->second->idle_since < v->second->idle_since) v = it;
+    return v;
+}
+
 // Workspace for `pairs` requests of geometry p: the idle one of that
 // geometry with the least room that holds them, else a new one (room for
 // the next power of two, at most max_batch) within the budget, evicting
-// idle workspaces of other geometries. Caller holds mu_.
+// the idle workspaces that have been idle longest (a mix of geometries keeps
+// its frequent ones; each eviction is a device-wide synchronising free and
+// each new workspace an allocation and fresh graphs). Caller holds mu_.
 int Engine::acquire(const sfft_params& p, int pairs, hipStream_t st, std::unique_ptr<Plan>& out,
                     bool* wait_for_memory) {
     *wait_for_memory = false;
@@ -140,7 +155,7 @@ int Engine::acquire(const sfft_params& p, int pairs, hipStream_t st, std::unique
         }
     }
     while (ctx_->budget && ctx_->used + need > ctx_->budget && !idle_.empty()) {
-        auto victim = idle_.begin();
+        auto victim = eviction_victim();
         destroy_plan(ctx_, victim->second);
         idle_.erase(victim);
     }
@@ -152,7 +167,7 @@ int Engine::acquire(const sfft_params& p, int pairs, hipStream_t st, std::unique
     // the device itself out of memory: free idle workspaces, then wait for
     // running requests to return theirs
     while (rc == SFFT_E_NOMEM && !idle_.empty()) {
-        auto victim = idle_.begin();
+        auto victim = eviction_victim();
         destroy_plan(ctx_, victim->second);
         idle_.erase(victim);
         rc = create_plan(ctx_, &p, out, cap, st);
@@ -176,8 +191,7 @@ void Engine::loop() {
                     status_[s.tickets[z]] = rc ? rc : flag_status(f);
                 }
                 s.tickets.clear();
-                auto key = key_of(&s.plan->p);
-                idle_.emplace(key, std::move(s.plan));
+                make_idle(std::move(s.plan));
                 s.busy = false;
                 done_cv_.notify_all();
             } else {
@@ -232,7 +246,7 @@ void Engine::loop() {
             for (size_t z = pick.size(); z-- > 0;) queue_.erase(queue_.begin() + (long)pick[z]);
             if (rc) {
                 for (uint64_t t : tickets) status_[t] = rc;
-                idle_.emplace(key_of(&pl->p), std::move(pl));
+                make_idle(std::move(pl));
                 done_cv_.notify_all();
             } else {
                 free_slot->plan = std::move(pl);

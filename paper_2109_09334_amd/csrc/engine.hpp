@@ -64,6 +64,10 @@ private:
     std::deque<Job> queue_;
     std::map<uint64_t, int> status_;
     std::multimap<PlanKey, std::unique_ptr<Plan>> idle_;
+    uint64_t idle_tick_ = 0;   // orders the idle workspaces by when they went idle
+    void make_idle(std::unique_ptr<Plan> pl);
+    // the idle workspace that has been idle longest
+    std::multimap<PlanKey, std::unique_ptr<Plan>>::iterator eviction_victim();
     std::vector<hipEvent_t> events_;   // free submit events
     std::mutex mu_;
     std::condition_variable cv_, done_cv_;

@@ -169,6 +169,8 @@ struct Plan {
     // noise decorrelation buffers (allocated on the plan's first use of it)
     char* dec = nullptr;
     size_t dec_bytes = 0;
+    // serving engine: when the workspace last went idle (eviction order)
+    uint64_t idle_since = 0;
 };
 
 int check_params(const sfft_params* p);
