@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--slots", type=int, default=6,
                     help="engine slots of the closed-loop served runs (4096^2 batches, C4)")
     ap.add_argument("--stream-slots", type=int, default=4,
