@@ -138,8 +138,24 @@ __device__ __forceinline__ void stage_panels(const double* __restrict__ L, int n
 __device__ __forceinline__ void tile_update(int n, double* __restrict__ L, int kp, int i0, int j0,
                                             double (*PI)[NBK + 1], double (*PJ)[NBK + 1]) {
     const int ni = min(NBK, n - i0), nj = min(NBK, n - j0);
-    stage_panels(L, n, kp, i0, ni, j0, nj, PI, PJ);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the tile's current values, loaded first and unconditionally (indices
+    // clamped into the matrix) so that they are all in flight together and
+    // behind the staging and the products (a load under a per-lane condition
+    // is a branch with its own wait)
+    double old[kStripsPerWave][kBlocksPerStrip][4];
+#pragma unroll
+    for (int t = 0; t < kStripsPerWave; ++t) {
+        const int jc = min(16 * strip_of(wv, t) + (lane & 15), nj - 1);
+#pragma unroll
+        for (int I = 0; I < kBlocksPerStrip; ++I)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * (rowblock0_of(wv) + I) + (lane >> 4) + 4 * q;
+                old[t][I][q] = L[(size_t)(i0 + min(i, ni - 1)) * n + j0 + jc];
+            }
+    }
+    stage_panels(L, n, kp, i0, ni, j0, nj, PI, PJ);
 #pragma unroll
     for (int t = 0; t < kStripsPerWave; ++t) {
         const int sc = strip_of(wv, t), I0 = rowblock0_of(wv);
@@ -152,7 +168,7 @@ __device__ __forceinline__ void tile_update(int n, double* __restrict__ L, int k
             for (int q = 0; q < 4; ++q) {
                 const int i = 16 * (I0 + I) + (lane >> 4) + 4 * q;
                 if (i < ni && jc < nj && !(i0 == j0 && jc > i))
-                    L[(size_t)(i0 + i) * n + j0 + jc] -= acc[I][q];
+                    L[(size_t)(i0 + i) * n + j0 + jc] = old[t][I][q] - acc[I][q];
             }
     }
 }
@@ -425,9 +441,16 @@ __global__ void __launch_bounds__(256) diag_finish_kernel(int n, double* __restr
     __shared__ double wrow[2][NBK];
     const int B = blockIdx.x, kb = B * NBK, nb = min(NBK, n - kb);
     const double* in = dfac + (size_t)B * NBK * NBK;
-    for (int t = threadIdx.x; t < NBK * NBK; t += blockDim.x) {
-        const int i = t >> 6, c = t & 63;
-        Lb[i][c] = (i < nb && c <= i && c < nb) ? in[i * NBK + c] : (i == c ? 1.0 : 0.0);
+    // the whole 64 x 64 block of dfac (always allocated) loaded at once,
+    // then masked: no load waits under a per-lane condition
+    constexpr int kPer = NBK * NBK / 256;   // launched with 256 threads
+    double v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) v[q] = in[threadIdx.x + 256 * q];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int t = threadIdx.x + 256 * q, i = t >> 6, c = t & 63;
+        Lb[i][c] = (i < nb && c <= i && c < nb) ? v[q] : (i == c ? 1.0 : 0.0);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
@@ -491,9 +514,18 @@ __global__ void __launch_bounds__(256) mirror_kernel(int n, double* __restrict__
     const int J = rem;
     const int i0 = I * NBK, j0 = J * NBK;   // J < I: the tile has 64 full columns
     const int ni = min(NBK, n - i0);
-    for (int k = threadIdx.x; k < NBK * NBK; k += blockDim.x) {
-        const int r = k >> 6, col = k & 63;
-        if (r < ni) t[r][col] = L[(size_t)(i0 + r) * n + j0 + col];
+    // every load issued before any is used (rows clamped into the matrix)
+    constexpr int kPer = NBK * NBK / 256;   // launched with 256 threads
+    double v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int k = threadIdx.x + 256 * q, r = k >> 6, col = k & 63;
+        v[q] = L[(size_t)(i0 + min(r, ni - 1)) * n + j0 + col];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int k = threadIdx.x + 256 * q, r = k >> 6, col = k & 63;
+        if (r < ni) t[r][col] = v[q];
     }
     __syncthreads();
     for (int k = threadIdx.x; k < NBK * NBK; k += blockDim.x) {
