@@ -262,6 +262,15 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
         for (int e = 0; e < kElemsPerThread; ++e) v[e] = mk(T(0), T(0));
     }
     line_dft<1, T, PL>(v, buf, lp, lt, twt);
+    // FP32 lines and images of a direct plan (N1 = 16 TL): the inverse goes
+    // through LDS so that each thread writes consecutive pixels
+    constexpr bool kQuadOut = sizeof(T) == 4 && sizeof(Tout) == 4 && !IsChirp<PL>::value;
+    if constexpr (kQuadOut) {
+        __syncthreads();   // the transform's last reads of buf
+#pragma unroll
+        for (int e = 0; e < kElemsPerThread; ++e) buf[lpad(lt + e * lp.tl)] = v[e];
+        __syncthreads();
+    }
     if (act) {
         const double inv = 1.0 / (double)n1;
         const int n0 = g.n0, w0 = g.w0, R = max(g.dk, g.db);
@@ -279,6 +288,61 @@ __global__ void __launch_bounds__(512) rowinv_kernel(Geom g, LinePlan lp,
         // together (one batch of loads in flight per power)
         constexpr int kChunk = 4;
         static_assert(kElemsPerThread % kChunk == 0, "chunked sky terms");
+        if constexpr (kQuadOut) {
+            // thread lt owns the four consecutive pixels x1 = 4 (lt + tl k)
+            // .. + 3 of both rows, k < 4 (from the line in LDS): 16-byte
+            // table loads and, on a 16-byte aligned image, 16-byte stores
+            const bool d16 = (reinterpret_cast<uintptr_t>(d) & 15) == 0;
+#pragma unroll
+            for (int k = 0; k < kElemsPerThread / kChunk; ++k) {
+                const int x1 = kChunk * (lt + k * lp.tl);
+                double ba[kChunk], bb[kChunk];
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) ba[q] = bb[q] = 0.0;
+                double pa = 1.0, pb = 1.0;
+                for (int r = 0; r < nsky; ++r) {
+                    const double2* yr = reinterpret_cast<const double2*>(sky + (size_t)r * n1 + x1);
+                    const double2 y01 = yr[0], y23 = yr[1];
+                    const double y[kChunk] = {y01.x, y01.y, y23.x, y23.y};
+#pragma unroll
+                    for (int q = 0; q < kChunk; ++q) {
+                        ba[q] += pa * y[q];
+                        bb[q] += pb * y[q];
+                    }
+                    pa *= ca;
+                    pb *= cb;
+                }
+                if (ra) {
+                    const double2* e = reinterpret_cast<const double2*>(ra + x1);
+                    const double2 e01 = e[0], e23 = e[1];
+                    ba[0] = e01.x, ba[1] = e01.y, ba[2] = e23.x, ba[3] = e23.y;
+                }
+                if (rb) {
+                    const double2* e = reinterpret_cast<const double2*>(rb + x1);
+                    const double2 e01 = e[0], e23 = e[1];
+                    bb[0] = e01.x, bb[1] = e01.y, bb[2] = e23.x, bb[3] = e23.y;
+                }
+                float oa[kChunk], ob[kChunk];
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) {
+                    const cx<T> u = buf[lpad(x1 + q)];
+                    oa[q] = float((double)u.re * inv - ba[q]);
+                    ob[q] = float((double)u.im * inv - bb[q]);
+                }
+                Tout* pa_ = d + (size_t)xa * n1 + x1;
+                Tout* pb_ = d + (size_t)xb * n1 + x1;
+                if (d16) {
+                    *reinterpret_cast<float4*>(pa_) = make_float4(oa[0], oa[1], oa[2], oa[3]);
+                    *reinterpret_cast<float4*>(pb_) = make_float4(ob[0], ob[1], ob[2], ob[3]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < kChunk; ++q) {
+                        pa_[q] = oa[q];
+                        pb_[q] = ob[q];
+                    }
+                }
+            }
+        } else
 #pragma unroll
         for (int e0 = 0; e0 < kElemsPerThread; e0 += kChunk) {
             double ba[kChunk], bb[kChunk];
